@@ -1,0 +1,56 @@
+"""Gate matrices (complex128, numpy) for the synthetic circuits.
+
+Conventions (the paper names the gate set but prints no matrices, so these are
+the readings used throughout; both the circuit file and every consumer take
+the matrices from here, so a phase convention cannot make the two sides
+disagree):
+
+* fSim(theta, phi) in the basis |00>,|01>,|10>,|11>:
+  [[1,0,0,0],[0,cos t,-i sin t,0],[0,-i sin t,cos t,0],[0,0,0,exp(-i phi)]]
+  (Sec. 4, Fig. 6 names fSim as the only two-qubit gate of Sycamore-53).
+* sqrt(P) = ((1+i) I + (1-i) P) / 2 for P in {X, Y, W}, W = (X+Y)/sqrt(2).
+* Haar unitaries: QR of a complex Ginibre matrix with the phase of R's
+  diagonal divided out (Mezzadri, "How to generate random matrices from the
+  classical compact groups", 2007).
+"""
+
+import numpy as np
+
+I2 = np.eye(2, dtype=np.complex128)
+X = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+Y = np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
+Z = np.array([[1, 0], [0, -1]], dtype=np.complex128)
+W = (X + Y) / np.sqrt(2.0)
+H = np.array([[1, 1], [1, -1]], dtype=np.complex128) / np.sqrt(2.0)
+CNOT = np.array([[1, 0, 0, 0],
+                 [0, 1, 0, 0],
+                 [0, 0, 0, 1],
+                 [0, 0, 1, 0]], dtype=np.complex128)
+
+
+def sqrt_pauli(p):
+    """Principal square root of an involutory Hermitian 2x2 matrix P."""
+    return ((1 + 1j) * I2 + (1 - 1j) * p) / 2.0
+
+
+SQRT_X = sqrt_pauli(X)
+SQRT_Y = sqrt_pauli(Y)
+SQRT_W = sqrt_pauli(W)
+ONE_QUBIT_SET = (SQRT_X, SQRT_Y, SQRT_W)
+ONE_QUBIT_NAMES = ("sqrt_x", "sqrt_y", "sqrt_w")
+
+
+def fsim(theta, phi):
+    c, s = np.cos(theta), np.sin(theta)
+    return np.array([[1, 0, 0, 0],
+                     [0, c, -1j * s, 0],
+                     [0, -1j * s, c, 0],
+                     [0, 0, 0, np.exp(-1j * phi)]], dtype=np.complex128)
+
+
+def haar_unitary(d, rng):
+    """Haar-random d x d unitary drawn from ``rng`` (numpy Generator)."""
+    z = (rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d))) / np.sqrt(2.0)
+    q, r = np.linalg.qr(z)
+    ph = np.diag(r) / np.abs(np.diag(r))
+    return q * ph[None, :]

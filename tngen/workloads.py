@@ -1,0 +1,79 @@
+"""The five synthetic workloads (seeded), each returned as a ``Workload``:
+circuit, tensor network, SSA path, sliced index ids and path statistics.
+
+1. plain      3x4 grid, depth 8, one amplitude, greedy path, no slicing.
+2. sliced     5x6 grid, depth 14, one amplitude, 6 sliced dim-2 indices
+              (64 slices) chosen to cap per-slice intermediates at 2^26.
+3. precision  53 active sites of a 6x9 grid (site (0,4) inactive), depth 12,
+              10 sliced indices (1024 slices), per-slice cap 2^30.
+4. bosonic    4x4 modes, depth 6, Fock cutoff 4, Haar two-mode gates,
+              2 sliced dim-4 indices (16 slices).
+5. gradient   4x5 grid, depth 10, trainable fSim(theta_i, phi_i) on every
+              two-qubit gate, batch of 256 outcome strings.
+
+Sycamore-style circuits stand in for the Sycamore-53 circuit files and the
+GBS-like network for the GBS circuits of Sec. 4 (same gate counts per cycle
+and lattice shapes as described there; no external data is used).
+Seeds: circuit ``[seed, 0]``, outcomes ``[seed, 1]``, path trials
+``[seed, 2, t]``.
+"""
+
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+from . import circuits, network, slicing
+
+
+@dataclass
+class Workload:
+    name: str
+    circuit: object
+    tn: object
+    path: list
+    sliced: List[int]
+    stats: dict
+    outcome: Optional[np.ndarray] = None
+    batch: Optional[np.ndarray] = None
+    meta: dict = field(default_factory=dict)
+
+
+CONFIGS = {
+    "plain": dict(kind="grid", rows=3, cols=4, depth=8, n_slice=0),
+    "sliced": dict(kind="grid", rows=5, cols=6, depth=14, n_slice=6, cap_log2=26),
+    "precision": dict(kind="grid", rows=6, cols=9, depth=12, inactive=((0, 4),),
+                      n_slice=10, cap_log2=30),
+    "bosonic": dict(kind="gbs", rows=4, cols=4, depth=6, d=4, n_slice=2),
+    "gradient": dict(kind="grid", rows=4, cols=5, depth=10, batch=256, trainable=True,
+                     n_slice=0),
+}
+
+
+def build(name, seed=0, trials=None, **over):
+    cfg = dict(CONFIGS[name])
+    cfg.update(over)
+    kind = cfg.pop("kind")
+    n_slice = cfg.pop("n_slice", 0)
+    cap = cfg.pop("cap_log2", None)
+    batch_n = cfg.pop("batch", None)
+    trainable = cfg.pop("trainable", False)
+    n_trials = cfg.pop("trials", 8) if trials is None else trials
+    if kind == "grid":
+        circ = circuits.grid_rqc(cfg["rows"], cfg["cols"], cfg["depth"], seed,
+                                 inactive=cfg.get("inactive", ()), trainable=trainable)
+    else:
+        circ = circuits.gbs_like(cfg["rows"], cfg["cols"], cfg["depth"], seed, d=cfg["d"])
+    outcome = batch = None
+    if batch_n:
+        batch = circuits.random_bitstrings(circ.n, circ.d, batch_n, seed)
+        tn = network.circuit_network(circ, batch=batch)
+    else:
+        outcome = circuits.random_bitstrings(circ.n, circ.d, 1, seed)[0]
+        tn = network.circuit_network(circ, outcome=outcome)
+    tn = network.relabel_compact(tn)
+    path, sliced, st = slicing.search(tn.labels, tn.dims, tn.open,
+                                      n_slice=n_slice if n_slice else 0,
+                                      cap_log2=cap, trials=n_trials, seed=seed)
+    return Workload(name=name, circuit=circ, tn=tn, path=path, sliced=sliced, stats=st,
+                    outcome=outcome, batch=batch, meta=dict(seed=seed, cap_log2=cap))
