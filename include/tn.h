@@ -1,0 +1,207 @@
+/*
+ * tn.h -- C ABI of the sliced tensor-network contraction library (gfx950).
+ *
+ * The library computes the contraction of a tensor network of complex
+ * tensors along a given pairwise contraction path (Sec. 2.3, Eq. sequence),
+ * with a given set of sliced indices (Sec. 2.4, Eq. sliced_sum): the result
+ * is the sum over all slices of the sliced networks' contractions.  Work that
+ * does not depend on a slice is done once and reused by every slice
+ * (Sec. 3.2, Fig. 5, Eq. task_based_amplitude_flops).
+ *
+ * Conventions shared by every call
+ *   - Tensors are complex64 (interleaved re, im float32), row-major over the
+ *     tensor's index list: the last listed index varies fastest.
+ *   - Every index dimension is a power of two, 2 .. 65536.  An index that is
+ *     not open appears in exactly two tensors and is summed when they meet
+ *     (or kept and summed at the very end if it is sliced).  An open index
+ *     may appear in any number of tensors (e.g. a batch of outcome strings
+ *     shared by all output tensors); it is never summed and indexes the
+ *     output.
+ *   - Slice ids are mixed radix over the sliced indices in the order given at
+ *     plan creation, the first one most significant.
+ *   - Output buffers are complex128 (interleaved re, im float64), row-major
+ *     over the open indices in the order given at plan creation.
+ *   - Device pointers are HIP device pointers on the current device; the
+ *     stream argument is a hipStream_t (NULL = default stream).  All device
+ *     work is asynchronous on that stream.
+ *   - Ownership: the plan copies every host array it is given.  The caller
+ *     owns every device buffer (leaves, outputs, gradients, workspace); the
+ *     library never allocates or frees device memory on its own and never
+ *     keeps a device pointer past the call that received it.
+ *   - Errors: every call returns a tn_status; no call aborts and no C++
+ *     exception crosses this boundary.  tn_last_error() returns a message for
+ *     the last failing call on the calling thread.
+ *   - Concurrency: a plan is immutable after creation; it may be used by
+ *     concurrent calls on different streams with distinct workspaces.
+ */
+#ifndef TN_H_
+#define TN_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tn_plan_s* tn_plan_t;
+
+typedef enum {
+  TN_OK = 0,
+  TN_E_INVALID = 1,      /* malformed network, path, slice list or argument   */
+  TN_E_UNSUPPORTED = 2,  /* valid input outside what this build supports      */
+  TN_E_WORKSPACE = 3,    /* workspace smaller than tn_plan_info.workspace_bytes */
+  TN_E_OOM = 4,          /* host allocation failed                            */
+  TN_E_HIP = 5           /* a HIP runtime call or kernel launch failed        */
+} tn_status;
+
+typedef enum { TN_C64 = 0, TN_SPLIT_BF16 = 1 } tn_precision;
+
+typedef enum { TN_OUT_SUM = 0, TN_OUT_PER_SLICE = 1 } tn_out_mode;
+
+/* plan flags */
+#define TN_FLAG_NO_REUSE 1u   /* every slice recomputes every step (Eq. sliced_flops) */
+#define TN_FLAG_SIMPLE_KERNELS 2u /* force the plain per-element kernels (debug)     */
+
+typedef struct {
+  int32_t precision;          /* tn_precision                                       */
+  int32_t max_resident_bits;  /* cap on log2(slices computed together); -1 = auto   */
+  int64_t workspace_limit;    /* bytes the arena may use; 0 = no limit              */
+  uint32_t flags;             /* TN_FLAG_*                                          */
+  int32_t reserved[7];
+} tn_plan_options;
+
+typedef struct {
+  int32_t n_tensors, n_steps, n_index, n_sliced;
+  int32_t n_open_bits;            /* log2 of the output elements per slice         */
+  int32_t n_resident_bits;        /* log2 of slices contracted together in HBM     */
+  int32_t n_outer_bits;           /* log2 of outer iterations                       */
+  int32_t max_log2_per_slice;     /* largest per-slice intermediate, log2 elements  */
+  int32_t max_log2_resident;      /* largest intermediate as held in HBM, log2      */
+  int32_t n_launches;             /* kernel launches of one tn_contract (all slices) */
+  int64_t n_slices;
+  int64_t out_elems;              /* complex128 elements per output row             */
+  int64_t workspace_bytes;        /* bytes tn_contract needs                        */
+  int64_t workspace_backward_bytes; /* bytes tn_contract_backward needs             */
+  int64_t arena_bytes;            /* peak intermediate bytes (with deletion)        */
+  int64_t bytes_no_deletion;      /* intermediate bytes if nothing were freed       */
+  /* complex multiply-adds (one CMAC = 8 real flops) */
+  double cmac_reuse;              /* shared work done once, all slices resident     */
+  double cmac_noreuse;            /* N_sl x per-slice cost (Eq. sliced_flops)       */
+  double cmac_exec;               /* what tn_contract executes with this plan       */
+  double cmac_per_slice;          /* FLOP_sl of Eq. sliced_flops                    */
+  double f_sl;                    /* shared fraction of Eq. task_based_amplitude_flops */
+  double bytes_min_exec;          /* algorithmic HBM bytes of one tn_contract       */
+  /* where each slice's result lives in the root tensor (log2 strides):
+   * output bit j (lsb first, row-major over the open indices) at 2^root_open_log2[j];
+   * resident slice bit j at 2^root_res_log2[j], which is bit res_slicebit[j] of
+   * the slice id; outer iteration bit j is bit outer_slicebit[j] of the slice id. */
+  int8_t root_open_log2[48];
+  int8_t root_res_log2[48];
+  int8_t res_slicebit[48];
+  int8_t outer_slicebit[48];
+} tn_plan_info;
+
+/* One step as scheduled (tests, benchmarks, autotuning). */
+typedef struct {
+  int32_t a, b, c;            /* SSA ids: leaves 0..n-1, step k creates n+k       */
+  int32_t phase;              /* 0: once, 1: once per outer iteration             */
+  int32_t kind;               /* kernel family chosen for the step                */
+  int32_t nb, nm, nn, nk;     /* bits of batch / row / column / summed indices    */
+  int32_t inst_bits;          /* log2 instances (slices) computed by this step    */
+  double cmac;                /* multiply-adds per execution                      */
+  /* log2 strides (elements) of each bit, least significant index bit first;
+   * A holds batch,m,k; B holds batch,k,n; C holds batch,m,n. */
+  int8_t sA_b[48], sB_b[48], sC_b[48];
+  int8_t sA_m[48], sC_m[48];
+  int8_t sB_n[48], sC_n[48];
+  int8_t sA_k[48], sB_k[48];
+  int64_t c_offset;           /* arena byte offset of the result                  */
+  int64_t c_bytes;
+} tn_step_info;
+
+/*
+ * Build a plan.  Arguments:
+ *   n_tensors, ranks[n_tensors]     leaf tensors and their ranks
+ *   index_ids[sum ranks]            index ids of every leaf, concatenated, each
+ *                                   in 0..n_index-1, in the leaf's axis order
+ *   index_dims[n_index]             dimension of every index (power of two)
+ *   open_ids[n_open]                open (output) indices
+ *   path[2*n_steps]                 SSA pairs, n_steps = n_tensors - 1 (Sec. 2.3)
+ *   sliced_ids[n_sliced]            sliced indices (Sec. 2.4), not open
+ *   opts                            may be NULL (defaults: complex64, auto)
+ * Returns TN_E_INVALID for a malformed network or path, TN_E_UNSUPPORTED for a
+ * dimension that is not a power of two or a tensor above 2^40 elements.
+ * Needs no GPU.
+ */
+tn_status tn_plan_create(int32_t n_tensors, const int32_t* ranks, const int32_t* index_ids,
+                         int32_t n_index, const int32_t* index_dims, int32_t n_open,
+                         const int32_t* open_ids, int32_t n_steps, const int32_t* path,
+                         int32_t n_sliced, const int32_t* sliced_ids,
+                         const tn_plan_options* opts, tn_plan_t* out);
+
+/* Plan statistics (Eqs. sliced_flops and task_based_amplitude_flops, memory
+ * with and without deletion of intermediates, Sec. 4 Fig. 8).  Needs no GPU. */
+tn_status tn_plan_query(tn_plan_t plan, tn_plan_info* out);
+
+/* Schedule of step ``step`` (0 .. n_steps-1, path order).  Needs no GPU. */
+tn_status tn_plan_step(tn_plan_t plan, int32_t step, tn_step_info* out);
+
+/*
+ * Contract.  leaves[n_tensors]: device complex64 tensors (read only).
+ * slice_ids[n_slice_ids]: slices to include (NULL, 0 = all, in id order).
+ * out_mode TN_OUT_SUM: out = sum of the selected slices, out_elems complex128.
+ * out_mode TN_OUT_PER_SLICE: out[i] = slice slice_ids[i] (or slice i),
+ *   n_slice_ids (or n_slices) rows of out_elems complex128.
+ * ws / ws_bytes: device workspace of at least info.workspace_bytes bytes.
+ * The sum over slices is accumulated in float64 in a fixed order, so results
+ * are reproducible run to run.
+ */
+tn_status tn_contract(tn_plan_t plan, const void* const* leaves, const int64_t* slice_ids,
+                      int64_t n_slice_ids, int32_t out_mode, void* out, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/*
+ * Adjoint of tn_contract with out_mode TN_OUT_SUM over all slices.
+ * grad_out: device complex128[out_elems], the gradient of a real loss with
+ * respect to the output in PyTorch's convention (dL/d conj(out)).
+ * grad_leaves[n_tensors]: device complex64 buffers shaped like the leaves;
+ * the gradient of each leaf is ADDED to it (NULL entries are skipped).
+ * ws / ws_bytes: at least info.workspace_backward_bytes.
+ * Returns TN_E_UNSUPPORTED when the plan needs outer iterations.
+ */
+tn_status tn_contract_backward(tn_plan_t plan, const void* const* leaves, const void* grad_out,
+                               void* const* grad_leaves, void* ws, size_t ws_bytes,
+                               void* stream);
+
+/*
+ * tn_contract with timing of one step: ev_start / ev_stop (hipEvent_t created
+ * by the caller with timing enabled) are recorded on ``stream`` right before
+ * the first launch and right after the last launch of step ``probe_step``
+ * (its first execution when it runs once per outer iteration).  Otherwise
+ * identical to tn_contract.
+ */
+tn_status tn_contract_probe(tn_plan_t plan, const void* const* leaves, const int64_t* slice_ids,
+                            int64_t n_slice_ids, int32_t out_mode, void* out, void* ws,
+                            size_t ws_bytes, void* stream, int32_t probe_step, void* ev_start,
+                            void* ev_stop);
+
+void tn_plan_destroy(tn_plan_t plan);
+
+const char* tn_last_error(void);
+
+/*
+ * Bit permutation of one tensor (the transpose of the TTGT decomposition,
+ * Sec. 3.1).  in / out: device complex64, 2^nbits elements each.  Element
+ * with index bits (i_0 .. i_{nbits-1}) is read at sum_j i_j 2^in_log2[j] and
+ * written at sum_j i_j 2^out_log2[j]; both stride lists must be permutations
+ * of 0..nbits-1.  nbits <= 40.
+ */
+tn_status tn_permute(const void* in, void* out, int32_t nbits, const int8_t* in_log2,
+                     const int8_t* out_log2, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TN_H_ */

@@ -1,0 +1,274 @@
+"""ctypes binding of the C ABI in include/tn.h (argument marshalling only).
+
+Every contraction step runs in the HIP library ``libtnmi.so`` built in this
+directory; if it is missing, importing the binding raises.  torch supplies
+device memory (leaves, outputs, workspace) and the current stream.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtnmi.so")
+
+TN_OK, TN_E_INVALID, TN_E_UNSUPPORTED, TN_E_WORKSPACE, TN_E_OOM, TN_E_HIP = range(6)
+TN_C64, TN_SPLIT_BF16 = 0, 1
+TN_OUT_SUM, TN_OUT_PER_SLICE = 0, 1
+TN_FLAG_NO_REUSE = 1
+TN_FLAG_SIMPLE_KERNELS = 2
+KIND_NAMES = {0: "simple", 1: "splitk", 2: "stream", 3: "gemm"}
+
+I8x48 = ctypes.c_int8 * 48
+
+
+class PlanOptions(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("max_resident_bits", ctypes.c_int32),
+                ("workspace_limit", ctypes.c_int64), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_int32 * 7)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in (
+        "n_tensors", "n_steps", "n_index", "n_sliced", "n_open_bits", "n_resident_bits",
+        "n_outer_bits", "max_log2_per_slice", "max_log2_resident", "n_launches")] + \
+        [(n, ctypes.c_int64) for n in (
+            "n_slices", "out_elems", "workspace_bytes", "workspace_backward_bytes",
+            "arena_bytes", "bytes_no_deletion")] + \
+        [(n, ctypes.c_double) for n in (
+            "cmac_reuse", "cmac_noreuse", "cmac_exec", "cmac_per_slice", "f_sl",
+            "bytes_min_exec")] + \
+        [(n, I8x48) for n in ("root_open_log2", "root_res_log2", "res_slicebit",
+                              "outer_slicebit")]
+
+
+class StepInfo(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in (
+        "a", "b", "c", "phase", "kind", "nb", "nm", "nn", "nk", "inst_bits")] + \
+        [("cmac", ctypes.c_double)] + \
+        [(n, I8x48) for n in ("sA_b", "sB_b", "sC_b", "sA_m", "sC_m", "sB_n", "sC_n",
+                              "sA_k", "sB_k")] + \
+        [("c_offset", ctypes.c_int64), ("c_bytes", ctypes.c_int64)]
+
+
+EXPORTS = ("tn_plan_create", "tn_plan_query", "tn_plan_step", "tn_contract",
+           "tn_contract_probe", "tn_contract_backward", "tn_plan_destroy", "tn_last_error",
+           "tn_permute")
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        L.tn_plan_create.restype = ctypes.c_int
+        L.tn_plan_create.argtypes = [ctypes.c_int32, i32p, i32p, ctypes.c_int32, i32p,
+                                     ctypes.c_int32, i32p, ctypes.c_int32, i32p, ctypes.c_int32,
+                                     i32p, ctypes.POINTER(PlanOptions), ctypes.POINTER(P)]
+        L.tn_plan_query.restype = ctypes.c_int
+        L.tn_plan_query.argtypes = [P, ctypes.POINTER(PlanInfo)]
+        L.tn_plan_step.restype = ctypes.c_int
+        L.tn_plan_step.argtypes = [P, ctypes.c_int32, ctypes.POINTER(StepInfo)]
+        L.tn_contract.restype = ctypes.c_int
+        L.tn_contract.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_int64),
+                                  ctypes.c_int64, ctypes.c_int32, P, P, ctypes.c_size_t, P]
+        L.tn_contract_probe.restype = ctypes.c_int
+        L.tn_contract_probe.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.c_int64, ctypes.c_int32, P, P, ctypes.c_size_t, P,
+                                        ctypes.c_int32, P, P]
+        L.tn_contract_backward.restype = ctypes.c_int
+        L.tn_contract_backward.argtypes = [P, ctypes.POINTER(P), P, ctypes.POINTER(P), P,
+                                           ctypes.c_size_t, P]
+        L.tn_plan_destroy.restype = None
+        L.tn_plan_destroy.argtypes = [P]
+        L.tn_last_error.restype = ctypes.c_char_p
+        L.tn_last_error.argtypes = []
+        L.tn_permute.restype = ctypes.c_int
+        L.tn_permute.argtypes = [P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int8),
+                                 ctypes.POINTER(ctypes.c_int8), P]
+        _lib = L
+    return _lib
+
+
+class TnError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"tn status {status}: {msg}")
+        self.status = status
+
+
+def _check(status):
+    if status != TN_OK:
+        raise TnError(status, lib().tn_last_error().decode())
+
+
+def _i32(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """A contraction plan (``tn_plan_create``).
+
+    ``labels``: index ids of each leaf (dense ids 0..n_index-1); ``dims``:
+    mapping or sequence id -> dimension; ``open_ids``: output indices;
+    ``path``: SSA pairs; ``sliced``: sliced index ids.
+    """
+
+    def __init__(self, labels, dims, open_ids, path, sliced=(), precision="c64",
+                 max_resident_bits=-1, workspace_limit=0, no_reuse=False, simple=False):
+        n_index = (max(dims) + 1) if isinstance(dims, dict) else len(dims)
+        dim_arr = [dims[i] for i in range(n_index)]
+        ranks, r_p = _i32([len(l) for l in labels])
+        ids, ids_p = _i32([i for l in labels for i in l] or [0])
+        darr, d_p = _i32(dim_arr or [2])
+        op, op_p = _i32(list(open_ids) or [0])
+        pa, pa_p = _i32([x for pr in path for x in pr] or [0])
+        sl, sl_p = _i32(list(sliced) or [0])
+        opts = PlanOptions()
+        opts.precision = {"c64": TN_C64, "split_bf16": TN_SPLIT_BF16}[precision]
+        opts.max_resident_bits = max_resident_bits
+        opts.workspace_limit = workspace_limit
+        opts.flags = (TN_FLAG_NO_REUSE if no_reuse else 0) | (TN_FLAG_SIMPLE_KERNELS if simple else 0)
+        h = ctypes.c_void_p()
+        _check(lib().tn_plan_create(len(labels), r_p, ids_p, n_index, d_p, len(open_ids), op_p,
+                                    len(path), pa_p, len(sliced), sl_p, ctypes.byref(opts),
+                                    ctypes.byref(h)))
+        self._h = h
+        self.n_tensors = len(labels)
+        self.labels = [list(l) for l in labels]
+        self.dims = dim_arr
+        self.open_ids = list(open_ids)
+        self.sliced = list(sliced)
+        self.precision = precision
+        self._ws = None
+        self._ws_bwd = None
+
+    @classmethod
+    def from_network(cls, tn, path, sliced=(), **kw):
+        return cls(tn.labels, tn.dims, tn.open, path, sliced, **kw)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.tn_plan_destroy(h)
+            self._h = None
+
+    def info(self):
+        inf = PlanInfo()
+        _check(lib().tn_plan_query(self._h, ctypes.byref(inf)))
+        d = {}
+        for name, _ in PlanInfo._fields_:
+            v = getattr(inf, name)
+            d[name] = list(v) if isinstance(v, ctypes.Array) else v
+        return d
+
+    def step(self, k):
+        s = StepInfo()
+        _check(lib().tn_plan_step(self._h, k, ctypes.byref(s)))
+        d = {}
+        for name, _ in StepInfo._fields_:
+            v = getattr(s, name)
+            d[name] = list(v) if isinstance(v, ctypes.Array) else v
+        for cls_, keys in (("nb", ("sA_b", "sB_b", "sC_b")), ("nm", ("sA_m", "sC_m")),
+                           ("nn", ("sB_n", "sC_n")), ("nk", ("sA_k", "sB_k"))):
+            for key in keys:
+                d[key] = d[key][:d[cls_]]
+        d["kind_name"] = KIND_NAMES.get(d["kind"], "?")
+        return d
+
+    def steps(self):
+        return [self.step(k) for k in range(self.n_tensors - 1)]
+
+    def _workspace(self, nbytes, device, attr):
+        import torch
+        ws = getattr(self, attr)
+        if ws is None or ws.numel() < nbytes or ws.device != device:
+            ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+            setattr(self, attr, ws)
+        return ws
+
+    def _leaf_ptrs(self, leaves):
+        import torch
+        if len(leaves) != self.n_tensors:
+            raise ValueError(f"expected {self.n_tensors} leaves, got {len(leaves)}")
+        dev = leaves[0].device
+        for t, x in enumerate(leaves):
+            if x.dtype != torch.complex64 or not x.is_contiguous() or x.device != dev:
+                raise ValueError(f"leaf {t} must be a contiguous complex64 tensor on {dev}")
+            if x.numel() != int(np.prod([self.dims[i] for i in self.labels[t]], dtype=np.int64)):
+                raise ValueError(f"leaf {t} has {x.numel()} elements, network says otherwise")
+        arr = (ctypes.c_void_p * self.n_tensors)(*[x.data_ptr() for x in leaves])
+        return arr, dev
+
+    def contract(self, leaves, slice_ids=None, per_slice=False, stream=None, out=None,
+                 probe=None):
+        """complex128 result: sum over the selected slices, or one row per slice.
+        ``probe=(step, start_event, stop_event)`` times one step with the
+        given torch.cuda.Event pair (tn_contract_probe)."""
+        import torch
+        inf = self.info()
+        arr, dev = self._leaf_ptrs(leaves)
+        ws = self._workspace(inf["workspace_bytes"], dev, "_ws")
+        shape = [self.dims[i] for i in self.open_ids]
+        if slice_ids is not None:
+            sids = np.ascontiguousarray(np.asarray(slice_ids, dtype=np.int64))
+            sp = sids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+            nsel = len(sids)
+        else:
+            sids, sp, nsel = None, None, 0
+        rows = (nsel if nsel else inf["n_slices"]) if per_slice else None
+        full = ([rows] if per_slice else []) + shape
+        if out is None:
+            out = torch.empty(full, dtype=torch.complex128, device=dev)
+        mode = TN_OUT_PER_SLICE if per_slice else TN_OUT_SUM
+        args = (self._h, arr, sp, nsel, mode, ctypes.c_void_p(out.data_ptr()),
+                ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream))
+        if probe is None:
+            _check(lib().tn_contract(*args))
+        else:
+            step, e0, e1 = probe
+            _check(lib().tn_contract_probe(*args, step, ctypes.c_void_p(e0.cuda_event),
+                                           ctypes.c_void_p(e1.cuda_event)))
+        return out
+
+    def backward(self, leaves, grad_out, grad_leaves, stream=None):
+        """Adds d(loss)/d(leaf) (PyTorch convention) into ``grad_leaves``."""
+        import torch
+        inf = self.info()
+        arr, dev = self._leaf_ptrs(leaves)
+        ws = self._workspace(inf["workspace_backward_bytes"], dev, "_ws_bwd")
+        g = grad_out.to(torch.complex128).contiguous()
+        garr = (ctypes.c_void_p * self.n_tensors)(
+            *[(x.data_ptr() if x is not None else None) for x in grad_leaves])
+        _check(lib().tn_contract_backward(self._h, arr, ctypes.c_void_p(g.data_ptr()), garr,
+                                          ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                          _stream_ptr(stream)))
+        return grad_leaves
+
+
+def permute(x, in_log2, out_log2, out=None, stream=None):
+    """Bit permutation of a complex64 device tensor (``tn_permute``)."""
+    import torch
+    nbits = len(in_log2)
+    if x.numel() != (1 << nbits) or x.dtype != torch.complex64 or not x.is_contiguous():
+        raise ValueError("x must be a contiguous complex64 tensor of 2^nbits elements")
+    if out is None:
+        out = torch.empty_like(x)
+    a = (ctypes.c_int8 * max(nbits, 1))(*in_log2)
+    b = (ctypes.c_int8 * max(nbits, 1))(*out_log2)
+    _check(lib().tn_permute(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), nbits,
+                            a, b, _stream_ptr(stream)))
+    return out

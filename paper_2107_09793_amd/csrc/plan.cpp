@@ -1,0 +1,566 @@
+// Contraction plan (host only).
+//
+// Bit model: every index of dimension 2^w is w bits.  A tensor is addressed
+// by its bits, each with a power-of-two stride, so every transpose of the
+// TTGT decomposition (Sec. 3.1) is a bit permutation and every operand of a
+// step can be read in place through its bit strides.
+//
+// Slicing with shared work (Sec. 2.4, Sec. 3.2): a sliced index is never
+// summed where its two tensors meet; it stays a bit of every node above them
+// and is summed at the very end.  A node therefore carries exactly the sliced
+// bits of the leaves below it -- its instance set S_v -- and is computed for
+// 2^|S_v| instances instead of once per slice; a node with S_v empty is the
+// shared work of Fig. 5 and runs once.  In a step, a sliced bit held by both
+// operands is a batch bit, one held by one operand folds into that operand's
+// free (row or column) bits.
+//
+// Resident / outer split (Sec. 4, Fig. 8 discussion: only a subset of slices
+// is held in memory, its size fixed a priori): the sliced indices are split
+// into resident ones (kept as bits in HBM) and outer ones (looped over).
+// Steps that depend on no outer index run once and their results stay
+// resident for all outer iterations; the others run once per iteration.
+//
+// Deletion of intermediates (Fig. 8): every result is freed after its single
+// consumer ran; arena offsets come from a best-fit allocator simulated here.
+#include "plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <map>
+#include <numeric>
+
+namespace tn {
+namespace {
+
+using Bits = std::vector<int32_t>;
+
+Bits inter(const Bits& a, const Bits& b) {
+  Bits r;
+  std::set_intersection(a.begin(), a.end(), b.begin(), b.end(), std::back_inserter(r));
+  return r;
+}
+Bits unite(const Bits& a, const Bits& b) {
+  Bits r;
+  std::set_union(a.begin(), a.end(), b.begin(), b.end(), std::back_inserter(r));
+  return r;
+}
+Bits minus(const Bits& a, const Bits& b) {
+  Bits r;
+  std::set_difference(a.begin(), a.end(), b.begin(), b.end(), std::back_inserter(r));
+  return r;
+}
+
+int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+// Best-fit arena with coalescing free list.
+struct Arena {
+  std::map<int64_t, int64_t> free_;  // offset -> size
+  int64_t top = 0;
+  int64_t alloc(int64_t bytes) {
+    bytes = align_up(std::max<int64_t>(bytes, 256), 256);
+    auto best = free_.end();
+    for (auto it = free_.begin(); it != free_.end(); ++it)
+      if (it->second >= bytes && (best == free_.end() || it->second < best->second)) best = it;
+    if (best != free_.end()) {
+      int64_t off = best->first, sz = best->second;
+      free_.erase(best);
+      if (sz > bytes) free_[off + bytes] = sz - bytes;
+      return off;
+    }
+    // grow; absorb a trailing free block
+    if (!free_.empty()) {
+      auto last = std::prev(free_.end());
+      if (last->first + last->second == top) {
+        int64_t off = last->first;
+        free_.erase(last);
+        top = off + bytes;
+        return off;
+      }
+    }
+    int64_t off = top;
+    top += bytes;
+    return off;
+  }
+  void release(int64_t off, int64_t bytes) {
+    bytes = align_up(std::max<int64_t>(bytes, 256), 256);
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+struct Layout {  // executed bits of a node with strides (bit id -> log2 stride)
+  std::map<int32_t, int8_t> s;
+};
+
+}  // namespace
+
+// Kernel family for a step of the given shape.
+static int32_t choose_kind(int nb, int nm, int nn, int nk, uint32_t flags, int32_t* chunks,
+                           int64_t* scratch) {
+  int out_bits = nb + nm + nn;
+  *chunks = 0;
+  *scratch = 0;
+  if (nk >= 8 && out_bits <= 12) {
+    int cl = std::max(8, nk - 10);  // log2 chunk length
+    if (cl > nk) cl = nk;
+    *chunks = 1 << (nk - cl);
+    *scratch = (int64_t)8 << (out_bits + (nk - cl));
+    return KIND_SPLITK;
+  }
+  if (flags & 2u) return KIND_SIMPLE;
+  if (nk <= 4 && nn <= 4 && nb <= 12) return KIND_STREAM;
+  return KIND_SIMPLE;
+}
+
+// Build schedule for a given outer set; fills steps, sched, memory, stats.
+static void schedule(Plan& p) {
+  const int n = p.n_tensors;
+  const int nsteps = n - 1;
+  const int nn_nodes = n + nsteps;
+  bool no_reuse = p.flags & 1u;
+  p.bit_outer.assign(p.n_bits, 0);
+  for (int e : p.outer_idx)
+    for (int j = 0; j < p.index_w[e]; ++j) p.bit_outer[p.index_bit0[e] + j] = 1;
+  Bits outer_bits_set;
+  for (int b = 0; b < p.n_bits; ++b)
+    if (p.bit_outer[b]) outer_bits_set.push_back(b);
+
+  p.node_ebits.assign(nn_nodes, {});
+  p.node_layout.assign(nn_nodes, {});
+  p.node_log2s.assign(nn_nodes, {});
+  p.node_phase.assign(nn_nodes, 0);
+  std::vector<Layout> lay(nn_nodes);
+
+  // leaves: executed layout = leaf layout without outer bits
+  for (int t = 0; t < n; ++t) {
+    LeafDesc& L = p.leaves[t];
+    L.outer_bits.clear();
+    L.outer_log2s.clear();
+    for (size_t i = 0; i < L.bits.size(); ++i) {
+      int b = L.bits[i];
+      if (p.bit_outer[b]) {
+        L.outer_bits.push_back(b);
+        L.outer_log2s.push_back(L.log2s[i]);
+      } else {
+        lay[t].s[b] = L.log2s[i];
+        p.node_layout[t].push_back(b);
+      }
+    }
+    p.node_ebits[t] = minus(p.node_bits[t], outer_bits_set);
+    p.node_phase[t] = L.outer_bits.empty() ? 0 : 1;
+  }
+
+  p.steps.assign(nsteps, StepDesc());
+  for (int k = 0; k < nsteps; ++k) {
+    int a = p.path[2 * k], b = p.path[2 * k + 1], v = n + k;
+    StepDesc& S = p.steps[k];
+    // the larger operand is A (rows); the smaller B (columns)
+    if (p.node_ebits[b].size() > p.node_ebits[a].size()) std::swap(a, b);
+    S.a = a;
+    S.b = b;
+    S.c = v;
+    const Bits& eA = p.node_ebits[a];
+    const Bits& eB = p.node_ebits[b];
+    Bits common = inter(eA, eB);
+    Bits batch, K;
+    for (int x : common) (p.bit_kept[x] ? batch : K).push_back(x);
+    Bits M = minus(eA, common), N = minus(eB, common);
+    auto by = [&](Bits v2, const Layout& L) {
+      std::sort(v2.begin(), v2.end(), [&](int x, int y) { return L.s.at(x) < L.s.at(y); });
+      return v2;
+    };
+    M = by(M, lay[a]);
+    N = by(N, lay[b]);
+    batch = by(batch, lay[a]);
+    K = by(K, lay[a]);
+    // result layout, least significant first: columns, rows, batch
+    Bits clayout;
+    clayout.insert(clayout.end(), N.begin(), N.end());
+    clayout.insert(clayout.end(), M.begin(), M.end());
+    clayout.insert(clayout.end(), batch.begin(), batch.end());
+    for (size_t i = 0; i < clayout.size(); ++i) lay[v].s[clayout[i]] = (int8_t)i;
+    p.node_layout[v] = clayout;
+    p.node_ebits[v] = unite(unite(batch, M), N);
+    std::sort(p.node_ebits[v].begin(), p.node_ebits[v].end());
+    auto fill = [&](const Bits& cls, const Layout& L, std::vector<int8_t>& out) {
+      out.clear();
+      for (int x : cls) out.push_back(L.s.at(x));
+    };
+    fill(batch, lay[a], S.bA);
+    fill(batch, lay[b], S.bB);
+    fill(batch, lay[v], S.bC);
+    fill(M, lay[a], S.mA);
+    fill(M, lay[v], S.mC);
+    fill(N, lay[b], S.nB);
+    fill(N, lay[v], S.nC);
+    fill(K, lay[a], S.kA);
+    fill(K, lay[b], S.kB);
+    int nb = (int)batch.size(), nm = (int)M.size(), nnb = (int)N.size(), nk = (int)K.size();
+    S.cmac = std::ldexp(1.0, nb + nm + nnb + nk);
+    S.c_bytes = (int64_t)8 << (nb + nm + nnb);
+    S.kind = choose_kind(nb, nm, nnb, nk, p.flags, &S.splitk_chunks, &S.scratch_bytes);
+    // instance bits all-resident: sliced bits of the operands
+    Bits u = unite(p.node_bits[a], p.node_bits[b]);
+    int sv = 0;
+    for (int x : u) sv += p.bit_sliced[x];
+    S.inst_bits = sv;
+    bool dep_outer = !inter(unite(p.node_bits[a], p.node_bits[b]), outer_bits_set).empty();
+    p.node_phase[v] = (no_reuse || dep_outer) ? 1 : 0;
+    S.phase = p.node_phase[v];
+  }
+  const int root = nn_nodes - 1;
+
+  // schedule: phase 0 in path order, then phase 1 in path order
+  p.sched.clear();
+  for (int k = 0; k < nsteps; ++k)
+    if (p.steps[k].phase == 0) p.sched.push_back(k);
+  p.n_phase0 = (int32_t)p.sched.size();
+  for (int k = 0; k < nsteps; ++k)
+    if (p.steps[k].phase == 1) p.sched.push_back(k);
+
+  // arena
+  Arena ar;
+  p.bytes_no_deletion = 0;
+  p.scratch_bytes = 0;
+  for (size_t pos = 0; pos < p.sched.size(); ++pos) {
+    StepDesc& S = p.steps[p.sched[pos]];
+    S.c_off = ar.alloc(S.c_bytes);
+    p.bytes_no_deletion += align_up(S.c_bytes, 256);
+    p.scratch_bytes = std::max(p.scratch_bytes, S.scratch_bytes);
+    for (int x : {S.a, S.b}) {
+      if (x < n) continue;
+      const StepDesc& X = p.steps[x - n];
+      if (X.phase == S.phase) ar.release(X.c_off, X.c_bytes);
+    }
+  }
+  p.arena_bytes = ar.top;
+
+  // root / output description
+  p.root_open_log2.clear();
+  p.root_res_log2.clear();
+  p.res_slicebit.clear();
+  p.outer_slicebit.clear();
+  p.outer_bit_ids.clear();
+  const Layout& RL = lay[root];
+  // output bits: open indices row-major, last open index fastest
+  for (int oi = (int)p.open_ids.size() - 1; oi >= 0; --oi) {
+    int e = p.open_ids[oi];
+    for (int j = 0; j < p.index_w[e]; ++j) p.root_open_log2.push_back(RL.s.at(p.index_bit0[e] + j));
+  }
+  // slice-id bits: last sliced index least significant
+  int pos = 0;
+  for (int si = (int)p.sliced_ids.size() - 1; si >= 0; --si) {
+    int e = p.sliced_ids[si];
+    for (int j = 0; j < p.index_w[e]; ++j, ++pos) {
+      int bit = p.index_bit0[e] + j;
+      if (p.bit_outer[bit]) {
+        p.outer_slicebit.push_back(pos);
+        p.outer_bit_ids.push_back(bit);
+      } else {
+        p.root_res_log2.push_back(RL.s.at(bit));
+        p.res_slicebit.push_back(pos);
+      }
+    }
+  }
+  p.outer_bits = (int32_t)p.outer_slicebit.size();
+  p.resident_bits = (int32_t)p.res_slicebit.size();
+  p.open_bits = (int32_t)p.root_open_log2.size();
+
+  // statistics
+  double iters = std::ldexp(1.0, p.outer_bits);
+  p.cmac_exec = 0;
+  p.bytes_min_exec = 0;
+  p.max_log2_res = 0;
+  int launches0 = 0, launches1 = 0;
+  for (int k = 0; k < nsteps; ++k) {
+    const StepDesc& S = p.steps[k];
+    double mult = S.phase ? iters : 1.0;
+    p.cmac_exec += mult * S.cmac;
+    double ea = std::ldexp(1.0, (int)p.node_ebits[S.a].size());
+    double eb = std::ldexp(1.0, (int)p.node_ebits[S.b].size());
+    double ec = std::ldexp(1.0, (int)p.node_ebits[S.c].size());
+    p.bytes_min_exec += mult * 8.0 * (ea + eb + ec);
+    p.max_log2_res = std::max(p.max_log2_res, (int32_t)p.node_ebits[S.c].size());
+    int l = (S.kind == KIND_SPLITK) ? 2 : 1;
+    (S.phase ? launches1 : launches0) += l;
+  }
+  p.n_launches = launches0 + (int32_t)iters * (launches1 + 1) + 1;
+  int64_t ctrl = align_up((int64_t)4 << p.resident_bits, 256);
+  p.ctrl_bytes = ctrl;
+  p.workspace_bytes = align_up(p.arena_bytes, 256) + align_up(p.scratch_bytes, 256) + ctrl;
+
+  // backward: all forward results kept (checkpointing everything), gradient
+  // buffers of intermediates allocated when produced and freed after use.
+  p.bwd_fwd_off.assign(nn_nodes, -1);
+  p.bwd_grad_off.assign(nn_nodes, -1);
+  if (nsteps == 0) {
+    p.bwd_arena_bytes = 0;
+    p.workspace_bwd_bytes = 256;
+    return;
+  }
+  int64_t top = 0;
+  for (int k : p.sched) {
+    p.bwd_fwd_off[n + k] = top;
+    top += align_up(p.steps[k].c_bytes, 256);
+  }
+  Arena ga;
+  ga.top = top;
+  p.bwd_grad_off[root] = ga.alloc(p.steps[root - n].c_bytes);
+  for (int i = (int)p.sched.size() - 1; i >= 0; --i) {
+    const StepDesc& S = p.steps[p.sched[i]];
+    for (int x : {S.a, S.b})
+      if (x >= n) p.bwd_grad_off[x] = ga.alloc(p.steps[x - n].c_bytes);
+    ga.release(p.bwd_grad_off[S.c], S.c_bytes);
+  }
+  p.bwd_arena_bytes = ga.top;
+  // backward split-k scratch: the adjoint products have the same bit counts
+  // permuted among classes; reserve the forward maximum or the backward one
+  int64_t bscr = 0;
+  for (const StepDesc& S : p.steps) {
+    int nb = (int)S.bA.size(), nm = (int)S.mA.size(), nnb = (int)S.nB.size(), nk = (int)S.kA.size();
+    int32_t ch;
+    int64_t sc;
+    choose_kind(nb, nm, nk, nnb, p.flags, &ch, &sc);  // dA: rows m, cols k, sum n
+    bscr = std::max(bscr, sc);
+    choose_kind(nb, nk, nnb, nm, p.flags, &ch, &sc);  // dB: rows k, cols n, sum m
+    bscr = std::max(bscr, sc);
+  }
+  p.workspace_bwd_bytes = align_up(p.bwd_arena_bytes, 256) + align_up(bscr, 256) + 256;
+}
+
+std::string build_plan(Plan& p, int32_t n_tensors, const int32_t* ranks,
+                       const int32_t* index_ids, int32_t n_index, const int32_t* index_dims,
+                       int32_t n_open, const int32_t* open_ids, int32_t n_steps,
+                       const int32_t* path, int32_t n_sliced, const int32_t* sliced_ids,
+                       int32_t precision, int32_t max_resident_bits, int64_t ws_limit,
+                       uint32_t flags, bool* unsupported) {
+  *unsupported = false;
+  char buf[256];
+  if (n_tensors < 1) return "n_tensors must be >= 1";
+  if (n_index < 0 || n_open < 0 || n_sliced < 0) return "negative count";
+  if (!ranks || (n_index > 0 && !index_dims)) return "null array";
+  if (precision != PREC_C64 && precision != PREC_SPLIT_BF16) return "unknown precision";
+  p.n_tensors = n_tensors;
+  p.n_index = n_index;
+  p.precision = precision;
+  p.flags = flags;
+  p.index_dims.assign(index_dims, index_dims + n_index);
+  p.index_w.assign(n_index, 0);
+  p.index_bit0.assign(n_index, 0);
+  int nbits = 0;
+  for (int i = 0; i < n_index; ++i) {
+    int d = index_dims[i];
+    if (d < 2) {
+      snprintf(buf, sizeof buf, "index %d has dimension %d (< 2)", i, d);
+      return buf;
+    }
+    if ((d & (d - 1)) != 0 || d > 65536) {
+      *unsupported = true;
+      snprintf(buf, sizeof buf, "index %d has dimension %d (not a power of two <= 65536)", i, d);
+      return buf;
+    }
+    int w = 0;
+    while ((1 << w) < d) ++w;
+    p.index_w[i] = w;
+    p.index_bit0[i] = nbits;
+    nbits += w;
+  }
+  p.n_bits = nbits;
+  // leaves
+  p.leaf_index.assign(n_tensors, {});
+  std::vector<int> count(n_index, 0);
+  int64_t off = 0;
+  for (int t = 0; t < n_tensors; ++t) {
+    if (ranks[t] < 0) return "negative rank";
+    for (int j = 0; j < ranks[t]; ++j) {
+      int id = index_ids[off + j];
+      if (id < 0 || id >= n_index) {
+        snprintf(buf, sizeof buf, "tensor %d lists unknown index %d", t, id);
+        return buf;
+      }
+      for (int q : p.leaf_index[t])
+        if (q == id) {
+          snprintf(buf, sizeof buf, "tensor %d lists index %d twice", t, id);
+          return buf;
+        }
+      p.leaf_index[t].push_back(id);
+      count[id]++;
+    }
+    off += ranks[t];
+  }
+  p.open_ids.assign(open_ids, open_ids + n_open);
+  p.sliced_ids.assign(sliced_ids, sliced_ids + n_sliced);
+  std::vector<uint8_t> is_open(n_index, 0), is_sl(n_index, 0);
+  for (int e : p.open_ids) {
+    if (e < 0 || e >= n_index || is_open[e]) return "open index unknown or repeated";
+    is_open[e] = 1;
+  }
+  for (int e : p.sliced_ids) {
+    if (e < 0 || e >= n_index || is_sl[e]) return "sliced index unknown or repeated";
+    if (is_open[e]) return "an open index cannot be sliced";
+    is_sl[e] = 1;
+  }
+  for (int i = 0; i < n_index; ++i) {
+    if (is_open[i]) {
+      if (count[i] < 1) {
+        snprintf(buf, sizeof buf, "open index %d appears in no tensor", i);
+        return buf;
+      }
+    } else if (count[i] != 2) {
+      snprintf(buf, sizeof buf, "index %d appears in %d tensors (must be 2 unless open)", i,
+               count[i]);
+      return buf;
+    }
+  }
+  // path
+  if (n_steps != n_tensors - 1) return "path must have n_tensors - 1 steps";
+  if (n_steps > 0 && !path) return "null path";
+  p.path.assign(path, path + 2 * n_steps);
+  {
+    std::vector<uint8_t> used(n_tensors + n_steps, 0);
+    for (int k = 0; k < n_steps; ++k) {
+      int a = p.path[2 * k], b = p.path[2 * k + 1];
+      if (a < 0 || b < 0 || a >= n_tensors + k || b >= n_tensors + k || a == b || used[a] ||
+          used[b]) {
+        snprintf(buf, sizeof buf, "path step %d (%d, %d) is not a valid SSA pair", k, a, b);
+        return buf;
+      }
+      used[a] = used[b] = 1;
+    }
+  }
+  // bits
+  p.bit_kept.assign(nbits, 0);
+  p.bit_sliced.assign(nbits, 0);
+  for (int i = 0; i < n_index; ++i)
+    for (int j = 0; j < p.index_w[i]; ++j) {
+      p.bit_kept[p.index_bit0[i] + j] = is_open[i] || is_sl[i];
+      p.bit_sliced[p.index_bit0[i] + j] = is_sl[i];
+    }
+  p.leaves.assign(n_tensors, LeafDesc());
+  const int nn_nodes = n_tensors + n_steps;
+  p.node_bits.assign(nn_nodes, {});
+  for (int t = 0; t < n_tensors; ++t) {
+    LeafDesc& L = p.leaves[t];
+    int s = 0;
+    for (int ax = (int)p.leaf_index[t].size() - 1; ax >= 0; --ax) {
+      int e = p.leaf_index[t][ax];
+      for (int j = 0; j < p.index_w[e]; ++j) {
+        L.bits.push_back(p.index_bit0[e] + j);
+        L.log2s.push_back((int8_t)(s + j));
+      }
+      s += p.index_w[e];
+    }
+    if (s > kMaxTensorBits) {
+      *unsupported = true;
+      return "a leaf has more than 2^40 elements";
+    }
+    p.node_bits[t] = L.bits;
+    std::sort(p.node_bits[t].begin(), p.node_bits[t].end());
+  }
+  for (int k = 0; k < n_steps; ++k) {
+    const Bits& A = p.node_bits[p.path[2 * k]];
+    const Bits& B = p.node_bits[p.path[2 * k + 1]];
+    Bits common = inter(A, B);
+    Bits summed;
+    for (int x : common)
+      if (!p.bit_kept[x]) summed.push_back(x);
+    p.node_bits[n_tensors + k] = minus(unite(A, B), summed);
+  }
+  for (int x : p.node_bits[nn_nodes - 1])
+    if (!p.bit_kept[x]) return "the path leaves an index unsummed";
+
+  // all-resident statistics (independent of the outer split)
+  p.n_slices = 1;
+  int sl_bits = 0;
+  for (int e : p.sliced_ids) sl_bits += p.index_w[e];
+  p.sliced_bits = sl_bits;
+  if (sl_bits > 40) {
+    *unsupported = true;
+    return "more than 2^40 slices";
+  }
+  p.n_slices = (int64_t)1 << sl_bits;
+  p.cmac_reuse = p.cmac_sl = 0;
+  p.max_log2_sl = 0;
+  p.node_sv.assign(nn_nodes, 0);
+  for (int v = 0; v < nn_nodes; ++v)
+    for (int x : p.node_bits[v]) p.node_sv[v] += p.bit_sliced[x];
+  for (int k = 0; k < n_steps; ++k) {
+    Bits u = unite(p.node_bits[p.path[2 * k]], p.node_bits[p.path[2 * k + 1]]);
+    int sv = 0;
+    for (int x : u) sv += p.bit_sliced[x];
+    p.cmac_reuse += std::ldexp(1.0, (int)u.size());
+    p.cmac_sl += std::ldexp(1.0, (int)u.size() - sv);
+    int v = n_tensors + k;
+    p.max_log2_sl = std::max(p.max_log2_sl, (int32_t)p.node_bits[v].size() - p.node_sv[v]);
+  }
+  p.cmac_noreuse = p.cmac_sl * (double)p.n_slices;
+  p.f_sl = p.n_slices > 1 ? (p.cmac_noreuse - p.cmac_reuse) / ((double)(p.n_slices - 1) * p.cmac_sl)
+                          : 0.0;
+
+  // outer / resident split
+  p.outer_idx.clear();
+  if (flags & 1u) {
+    p.outer_idx = p.sliced_ids;
+  }
+  schedule(p);
+  auto too_big = [&](const Plan& q) {
+    if (max_resident_bits >= 0 && q.resident_bits > max_resident_bits) return true;
+    if (ws_limit > 0 && q.arena_bytes > ws_limit) return true;
+    if (q.max_log2_res > kMaxTensorBits) return true;
+    return false;
+  };
+  while (too_big(p)) {
+    // move the sliced index whose outer looping costs the least work
+    int best = -1;
+    double best_cost = 0;
+    int64_t best_peak = 0;
+    std::vector<int32_t> base = p.outer_idx;
+    for (int e : p.sliced_ids) {
+      if (std::find(base.begin(), base.end(), e) != base.end()) continue;
+      p.outer_idx = base;
+      p.outer_idx.push_back(e);
+      schedule(p);
+      double cost = p.cmac_exec;
+      if (best < 0 || cost < best_cost || (cost == best_cost && p.arena_bytes < best_peak)) {
+        best = e;
+        best_cost = cost;
+        best_peak = p.arena_bytes;
+      }
+    }
+    if (best < 0) {
+      p.outer_idx = base;
+      schedule(p);
+      *unsupported = true;
+      return "the workspace limit cannot be met even with every sliced index looped over";
+    }
+    p.outer_idx = base;
+    p.outer_idx.push_back(best);
+    schedule(p);
+  }
+  p.resident_idx.clear();
+  for (int e : p.sliced_ids)
+    if (std::find(p.outer_idx.begin(), p.outer_idx.end(), e) == p.outer_idx.end())
+      p.resident_idx.push_back(e);
+  for (const StepDesc& S : p.steps) {
+    if ((int)S.bA.size() > kMaxBits || (int)S.mA.size() > kMaxBits ||
+        (int)S.nB.size() > kMaxBits || (int)S.kA.size() > kMaxBits) {
+      *unsupported = true;
+      return "a step has more than 48 bits in one class";
+    }
+  }
+  return "";
+}
+
+}  // namespace tn

@@ -1,0 +1,103 @@
+// Contraction plan: everything the device schedule needs, computed on the
+// host once per (network, path, slices).  No HIP dependency.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace tn {
+
+constexpr int kMaxBits = 48;       // bits of one class in one step
+constexpr int kMaxTensorBits = 40; // elements of any executed tensor <= 2^40
+
+enum Kind : int32_t {
+  KIND_SIMPLE = 0,   // one thread per output element, full k loop
+  KIND_SPLITK = 1,   // few outputs, long k: chunked partial sums + fixed-order reduce
+  KIND_STREAM = 2,   // one large operand streamed past a small one held on chip
+  KIND_GEMM = 3,     // MFMA tiles with bit-gather operand loads
+};
+
+enum Precision : int32_t { PREC_C64 = 0, PREC_SPLIT_BF16 = 1 };
+
+struct StepDesc {
+  int32_t a, b, c;        // SSA ids
+  int32_t phase;          // 0 once, 1 per outer iteration
+  int32_t kind;
+  int32_t inst_bits;      // log2 instances of this step, all slices resident
+  std::vector<int8_t> bA, bB, bC, mA, mC, nB, nC, kA, kB;   // log2 strides
+  double cmac;            // multiply-adds per execution
+  int64_t c_off;          // arena byte offset of the result
+  int64_t c_bytes;
+  int64_t scratch_bytes;  // split-k partials
+  int32_t splitk_chunks;
+};
+
+struct LeafDesc {
+  std::vector<int32_t> bits;      // global bit ids (all), layout order lsb first
+  std::vector<int8_t> log2s;      // stride of each bit
+  std::vector<int32_t> outer_bits; // subset of bits fixed per outer iteration
+  std::vector<int8_t> outer_log2s;
+};
+
+struct Plan {
+  // input (copied)
+  int32_t n_tensors = 0, n_index = 0;
+  std::vector<std::vector<int32_t>> leaf_index;
+  std::vector<int32_t> index_dims, index_w, index_bit0;
+  std::vector<int32_t> open_ids, sliced_ids;
+  std::vector<int32_t> path;       // 2 * n_steps
+  int32_t precision = PREC_C64;
+  uint32_t flags = 0;
+
+  // derived
+  int32_t n_bits = 0;                        // global bits
+  std::vector<uint8_t> bit_kept;             // sliced or open
+  std::vector<uint8_t> bit_sliced, bit_outer;
+  std::vector<std::vector<int32_t>> node_bits;  // all-resident bit set (sorted)
+  std::vector<std::vector<int32_t>> node_ebits; // executed bit set (outer removed)
+  std::vector<std::vector<int8_t>> node_log2s;  // stride per executed bit (same order)
+  std::vector<std::vector<int32_t>> node_layout; // executed bits in layout order (lsb first)
+  std::vector<int32_t> node_phase;
+  std::vector<int32_t> node_sv;              // |S_v| in bits (sliced bits below)
+  std::vector<LeafDesc> leaves;
+  std::vector<StepDesc> steps;               // path order
+  std::vector<int32_t> sched;                // step indices, execution order
+  int32_t n_phase0 = 0;                      // sched[0 .. n_phase0) run once
+
+  // outer / resident split (whole sliced indices)
+  std::vector<int32_t> outer_idx, resident_idx;   // sliced index ids
+  int32_t outer_bits = 0, resident_bits = 0, sliced_bits = 0, open_bits = 0;
+
+  // root / output
+  std::vector<int8_t> root_open_log2;     // stride in root of each output bit (lsb first)
+  std::vector<int8_t> root_res_log2;      // stride in root of each resident slice bit
+  std::vector<int32_t> res_slicebit;      // slice-id bit position of each resident bit
+  std::vector<int32_t> outer_slicebit;    // slice-id bit position of each outer bit
+  std::vector<int32_t> outer_bit_ids;     // global bit id of each outer bit (same order)
+
+  // memory
+  int64_t arena_bytes = 0, bytes_no_deletion = 0, scratch_bytes = 0;
+  int64_t ctrl_bytes = 0, workspace_bytes = 0, workspace_bwd_bytes = 0;
+  int64_t bwd_arena_bytes = 0;
+  std::vector<int64_t> bwd_fwd_off;   // backward: forward result offsets (nothing freed)
+  std::vector<int64_t> bwd_grad_off;  // backward: gradient buffer offsets per node
+
+  // statistics
+  double cmac_reuse = 0, cmac_noreuse = 0, cmac_exec = 0, cmac_sl = 0, f_sl = 0;
+  double bytes_min_exec = 0;
+  int32_t max_log2_sl = 0, max_log2_res = 0;
+  int64_t n_slices = 1;
+  int32_t n_launches = 0;
+};
+
+// Builds the plan; returns empty string on success, else an error message.
+// *unsupported is set when the input is valid but outside what is supported.
+std::string build_plan(Plan& p, int32_t n_tensors, const int32_t* ranks,
+                       const int32_t* index_ids, int32_t n_index, const int32_t* index_dims,
+                       int32_t n_open, const int32_t* open_ids, int32_t n_steps,
+                       const int32_t* path, int32_t n_sliced, const int32_t* sliced_ids,
+                       int32_t precision, int32_t max_resident_bits, int64_t ws_limit,
+                       uint32_t flags, bool* unsupported);
+
+}  // namespace tn

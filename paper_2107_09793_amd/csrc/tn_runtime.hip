@@ -1,0 +1,447 @@
+// C ABI (include/tn.h) and the host-side launcher.
+//
+// tn_contract walks the plan's schedule: steps that depend on no outer
+// sliced index run once, the others once per outer iteration, each as one or
+// two kernel launches on the caller's stream; after each iteration the
+// resident slice results are added in float64 (Eq. sliced_sum).
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/tn.h"
+#include "kernels_basic.h"
+#include "plan.h"
+
+struct tn_plan_s {
+  tn::Plan p;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+tn_status fail(tn_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define TN_HIP_CHECK(expr)                                                          \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return fail(TN_E_HIP, std::string(#expr " failed: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+inline unsigned grid_for(uint64_t work, uint64_t cap = 1u << 20) {
+  uint64_t g = (work + tnk::kBlock - 1) / tnk::kBlock;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+void copy_bits(int8_t* dst, const std::vector<int8_t>& src) {
+  for (size_t i = 0; i < src.size(); ++i) dst[i] = src[i];
+}
+
+tnk::StepArgs make_args(const tn::StepDesc& S) {
+  tnk::StepArgs a;
+  memset(&a, 0, sizeof a);
+  a.nb = (int32_t)S.bA.size();
+  a.nm = (int32_t)S.mA.size();
+  a.nn = (int32_t)S.nB.size();
+  a.nk = (int32_t)S.kA.size();
+  copy_bits(a.sA_b, S.bA);
+  copy_bits(a.sB_b, S.bB);
+  copy_bits(a.sC_b, S.bC);
+  copy_bits(a.sA_m, S.mA);
+  copy_bits(a.sC_m, S.mC);
+  copy_bits(a.sB_n, S.nB);
+  copy_bits(a.sC_n, S.nC);
+  copy_bits(a.sA_k, S.kA);
+  copy_bits(a.sB_k, S.kB);
+  return a;
+}
+
+template <int NK, int NN>
+void launch_stream_nn(const tnk::StepArgs& a, hipStream_t st) {
+  uint64_t rows = 1ull << (a.nb + a.nm);
+  hipLaunchKernelGGL((tnk::k_stream<NK, NN>), dim3(grid_for(rows)), dim3(tnk::kBlock), 0, st, a);
+}
+
+template <int NK>
+void launch_stream_k(const tnk::StepArgs& a, hipStream_t st) {
+  switch (a.nn) {
+    case 0: launch_stream_nn<NK, 0>(a, st); break;
+    case 1: launch_stream_nn<NK, 1>(a, st); break;
+    case 2: launch_stream_nn<NK, 2>(a, st); break;
+    case 3: launch_stream_nn<NK, 3>(a, st); break;
+    default: launch_stream_nn<NK, 4>(a, st); break;
+  }
+}
+
+// Launch one contraction (forward or adjoint) with the given kernel family.
+tn_status launch_step(int32_t kind, int32_t chunks, const tnk::StepArgs& a0, float2* scratch,
+                      hipStream_t st) {
+  tnk::StepArgs a = a0;
+  const uint64_t n_out = 1ull << (a.nb + a.nm + a.nn);
+  if (kind == tn::KIND_SPLITK) {
+    int cl = a.nk;
+    int64_t nch = chunks;
+    while ((1ll << (a.nk - cl)) < nch) --cl;
+    a.chunk_log2 = cl;
+    a.scratch = scratch;
+    dim3 grid((unsigned)nch, (unsigned)(n_out < 65536 ? n_out : 65536),
+              (unsigned)((n_out + 65535) / 65536));
+    hipLaunchKernelGGL(tnk::k_splitk_partial, grid, dim3(tnk::kBlock), 0, st, a);
+    hipLaunchKernelGGL(tnk::k_splitk_reduce, dim3(grid_for(n_out, 1u << 30)), dim3(tnk::kBlock),
+                       0, st, a, nch);
+  } else if (kind == tn::KIND_STREAM && a.nk <= 4 && a.nn <= 4) {
+    switch (a.nk) {
+      case 0: launch_stream_k<0>(a, st); break;
+      case 1: launch_stream_k<1>(a, st); break;
+      case 2: launch_stream_k<2>(a, st); break;
+      case 3: launch_stream_k<3>(a, st); break;
+      default: launch_stream_k<4>(a, st); break;
+    }
+  } else {
+    hipLaunchKernelGGL(tnk::k_simple, dim3(grid_for(n_out)), dim3(tnk::kBlock), 0, st, a);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(TN_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  return TN_OK;
+}
+
+// Kernel family and split-k chunks for an arbitrary (adjoint) shape, using
+// the plan's rule.
+int32_t kind_for(const tnk::StepArgs& a, uint32_t flags, int32_t* chunks) {
+  int out_bits = a.nb + a.nm + a.nn;
+  *chunks = 0;
+  if (a.nk >= 8 && out_bits <= 12) {
+    int cl = a.nk - 10 > 8 ? a.nk - 10 : 8;
+    if (cl > a.nk) cl = a.nk;
+    *chunks = 1 << (a.nk - cl);
+    return tn::KIND_SPLITK;
+  }
+  if (flags & TN_FLAG_SIMPLE_KERNELS) return tn::KIND_SIMPLE;
+  if (a.nk <= 4 && a.nn <= 4 && a.nb <= 12) return tn::KIND_STREAM;
+  return tn::KIND_SIMPLE;
+}
+
+struct Ctx {
+  const tn::Plan& p;
+  const void* const* leaves;
+  char* ws;
+  float2* scratch;
+  hipStream_t st;
+};
+
+const float2* node_ptr(const Ctx& c, int node, uint64_t outer_val) {
+  const tn::Plan& p = c.p;
+  if (node < p.n_tensors) {
+    const tn::LeafDesc& L = p.leaves[node];
+    int64_t off = 0;
+    for (size_t i = 0; i < L.outer_bits.size(); ++i) {
+      int bit = L.outer_bits[i];
+      for (int j = 0; j < p.outer_bits; ++j)
+        if (p.outer_bit_ids[j] == bit && ((outer_val >> j) & 1)) off += (int64_t)1 << L.outer_log2s[i];
+    }
+    return static_cast<const float2*>(c.leaves[node]) + off;
+  }
+  return reinterpret_cast<const float2*>(c.ws + p.steps[node - p.n_tensors].c_off);
+}
+
+struct Probe {
+  int32_t step = -1;
+  hipEvent_t start = nullptr, stop = nullptr;
+  bool done = false;
+};
+
+tn_status run_step(const Ctx& c, int k, uint64_t outer_val, Probe* probe = nullptr) {
+  const tn::Plan& p = c.p;
+  const tn::StepDesc& S = p.steps[k];
+  tnk::StepArgs a = make_args(S);
+  a.A = node_ptr(c, S.a, outer_val);
+  a.B = node_ptr(c, S.b, outer_val);
+  a.C = reinterpret_cast<float2*>(c.ws + S.c_off);
+  bool timed = probe && !probe->done && probe->step == k;
+  if (timed) TN_HIP_CHECK(hipEventRecord(probe->start, c.st));
+  tn_status s = launch_step(S.kind, S.splitk_chunks, a, c.scratch, c.st);
+  if (timed && s == TN_OK) {
+    TN_HIP_CHECK(hipEventRecord(probe->stop, c.st));
+    probe->done = true;
+  }
+  return s;
+}
+
+
+}  // namespace
+
+static tn_status contract_impl(tn_plan_t plan, const void* const* leaves,
+                               const int64_t* slice_ids, int64_t n_slice_ids, int32_t out_mode,
+                               void* out, void* ws, size_t ws_bytes, void* stream, Probe* probe);
+
+extern "C" {
+
+const char* tn_last_error(void) { return g_err.c_str(); }
+
+tn_status tn_plan_create(int32_t n_tensors, const int32_t* ranks, const int32_t* index_ids,
+                         int32_t n_index, const int32_t* index_dims, int32_t n_open,
+                         const int32_t* open_ids, int32_t n_steps, const int32_t* path,
+                         int32_t n_sliced, const int32_t* sliced_ids,
+                         const tn_plan_options* opts, tn_plan_t* out) {
+  if (!out) return fail(TN_E_INVALID, "out is NULL");
+  *out = nullptr;
+  tn_plan_options o;
+  memset(&o, 0, sizeof o);
+  o.max_resident_bits = -1;
+  if (opts) o = *opts;
+  try {
+    tn_plan_s* h = new tn_plan_s();
+    bool unsup = false;
+    std::string err = tn::build_plan(h->p, n_tensors, ranks, index_ids, n_index, index_dims,
+                                     n_open, open_ids, n_steps, path, n_sliced, sliced_ids,
+                                     o.precision, o.max_resident_bits, o.workspace_limit,
+                                     o.flags, &unsup);
+    if (!err.empty()) {
+      delete h;
+      return fail(unsup ? TN_E_UNSUPPORTED : TN_E_INVALID, err);
+    }
+    *out = h;
+    return TN_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(TN_E_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(TN_E_INVALID, e.what());
+  }
+}
+
+void tn_plan_destroy(tn_plan_t plan) { delete plan; }
+
+tn_status tn_plan_query(tn_plan_t plan, tn_plan_info* out) {
+  if (!plan || !out) return fail(TN_E_INVALID, "NULL argument");
+  const tn::Plan& p = plan->p;
+  memset(out, 0, sizeof *out);
+  out->n_tensors = p.n_tensors;
+  out->n_steps = p.n_tensors - 1;
+  out->n_index = p.n_index;
+  out->n_sliced = (int32_t)p.sliced_ids.size();
+  out->n_open_bits = p.open_bits;
+  out->n_resident_bits = p.resident_bits;
+  out->n_outer_bits = p.outer_bits;
+  out->max_log2_per_slice = p.max_log2_sl;
+  out->max_log2_resident = p.max_log2_res;
+  out->n_launches = p.n_launches;
+  out->n_slices = p.n_slices;
+  out->out_elems = (int64_t)1 << p.open_bits;
+  out->workspace_bytes = p.workspace_bytes;
+  out->workspace_backward_bytes = p.workspace_bwd_bytes;
+  out->arena_bytes = p.arena_bytes;
+  out->bytes_no_deletion = p.bytes_no_deletion;
+  out->cmac_reuse = p.cmac_reuse;
+  out->cmac_noreuse = p.cmac_noreuse;
+  out->cmac_exec = p.cmac_exec;
+  out->cmac_per_slice = p.cmac_sl;
+  out->f_sl = p.f_sl;
+  out->bytes_min_exec = p.bytes_min_exec;
+  copy_bits(out->root_open_log2, p.root_open_log2);
+  copy_bits(out->root_res_log2, p.root_res_log2);
+  for (int j = 0; j < p.resident_bits; ++j) out->res_slicebit[j] = (int8_t)p.res_slicebit[j];
+  for (int j = 0; j < p.outer_bits; ++j) out->outer_slicebit[j] = (int8_t)p.outer_slicebit[j];
+  return TN_OK;
+}
+
+tn_status tn_plan_step(tn_plan_t plan, int32_t step, tn_step_info* out) {
+  if (!plan || !out) return fail(TN_E_INVALID, "NULL argument");
+  const tn::Plan& p = plan->p;
+  if (step < 0 || step >= p.n_tensors - 1) return fail(TN_E_INVALID, "step out of range");
+  const tn::StepDesc& S = p.steps[step];
+  memset(out, 0, sizeof *out);
+  out->a = S.a;
+  out->b = S.b;
+  out->c = S.c;
+  out->phase = S.phase;
+  out->kind = S.kind;
+  out->nb = (int32_t)S.bA.size();
+  out->nm = (int32_t)S.mA.size();
+  out->nn = (int32_t)S.nB.size();
+  out->nk = (int32_t)S.kA.size();
+  out->inst_bits = S.inst_bits;
+  out->cmac = S.cmac;
+  copy_bits(out->sA_b, S.bA);
+  copy_bits(out->sB_b, S.bB);
+  copy_bits(out->sC_b, S.bC);
+  copy_bits(out->sA_m, S.mA);
+  copy_bits(out->sC_m, S.mC);
+  copy_bits(out->sB_n, S.nB);
+  copy_bits(out->sC_n, S.nC);
+  copy_bits(out->sA_k, S.kA);
+  copy_bits(out->sB_k, S.kB);
+  out->c_offset = S.c_off;
+  out->c_bytes = S.c_bytes;
+  return TN_OK;
+}
+
+tn_status tn_contract(tn_plan_t plan, const void* const* leaves, const int64_t* slice_ids,
+                      int64_t n_slice_ids, int32_t out_mode, void* out, void* ws,
+                      size_t ws_bytes, void* stream) {
+  return contract_impl(plan, leaves, slice_ids, n_slice_ids, out_mode, out, ws, ws_bytes, stream,
+                       nullptr);
+}
+
+tn_status tn_contract_probe(tn_plan_t plan, const void* const* leaves, const int64_t* slice_ids,
+                            int64_t n_slice_ids, int32_t out_mode, void* out, void* ws,
+                            size_t ws_bytes, void* stream, int32_t probe_step, void* ev_start,
+                            void* ev_stop) {
+  if (!plan) return fail(TN_E_INVALID, "NULL plan");
+  if (probe_step < 0 || probe_step >= plan->p.n_tensors - 1 || !ev_start || !ev_stop)
+    return fail(TN_E_INVALID, "bad probe step or events");
+  Probe pr;
+  pr.step = probe_step;
+  pr.start = static_cast<hipEvent_t>(ev_start);
+  pr.stop = static_cast<hipEvent_t>(ev_stop);
+  return contract_impl(plan, leaves, slice_ids, n_slice_ids, out_mode, out, ws, ws_bytes, stream,
+                       &pr);
+}
+
+}  // extern "C"
+
+static tn_status contract_impl(tn_plan_t plan, const void* const* leaves, const int64_t* slice_ids,
+                        int64_t n_slice_ids, int32_t out_mode, void* out, void* ws,
+                        size_t ws_bytes, void* stream, Probe* probe) {
+  if (!plan || !leaves || !out) return fail(TN_E_INVALID, "NULL argument");
+  const tn::Plan& p = plan->p;
+  if (out_mode != TN_OUT_SUM && out_mode != TN_OUT_PER_SLICE)
+    return fail(TN_E_INVALID, "unknown out_mode");
+  if ((int64_t)ws_bytes < p.workspace_bytes || (!ws && p.workspace_bytes > 0))
+    return fail(TN_E_WORKSPACE, "workspace smaller than tn_plan_info.workspace_bytes");
+  if (n_slice_ids < 0 || (n_slice_ids > 0 && !slice_ids))
+    return fail(TN_E_INVALID, "bad slice list");
+  for (int t = 0; t < p.n_tensors; ++t)
+    if (!leaves[t]) return fail(TN_E_INVALID, "NULL leaf pointer");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Ctx c{p, leaves, static_cast<char*>(ws),
+        reinterpret_cast<float2*>(static_cast<char*>(ws) + ((p.arena_bytes + 255) / 256) * 256), st};
+  const int64_t n_out = (int64_t)1 << p.open_bits;
+
+  // which (outer iteration, resident slice, row) triples are requested
+  const bool all = (n_slice_ids == 0);
+  std::map<uint64_t, std::vector<std::pair<int32_t, int32_t>>> sel;   // it -> (r, row)
+  if (!all) {
+    for (int64_t i = 0; i < n_slice_ids; ++i) {
+      int64_t s = slice_ids[i];
+      if (s < 0 || s >= p.n_slices) return fail(TN_E_INVALID, "slice id out of range");
+      uint64_t it = 0, r = 0;
+      for (int j = 0; j < p.outer_bits; ++j) it |= (uint64_t)((s >> p.outer_slicebit[j]) & 1) << j;
+      for (int j = 0; j < p.resident_bits; ++j) r |= (uint64_t)((s >> p.res_slicebit[j]) & 1) << j;
+      sel[it].push_back({(int32_t)r, (int32_t)i});
+    }
+  }
+  double2* outp = static_cast<double2*>(out);
+  if (out_mode == TN_OUT_SUM) {
+    hipLaunchKernelGGL(tnk::k_fill_c128, dim3(grid_for(n_out)), dim3(tnk::kBlock), 0, st, outp,
+                       n_out);
+    TN_HIP_CHECK(hipGetLastError());
+  }
+  // shared work: steps that depend on no outer index, once
+  for (int i = 0; i < p.n_phase0; ++i) {
+    tn_status s = run_step(c, p.sched[i], 0, probe);
+    if (s != TN_OK) return s;
+  }
+  const uint64_t n_it = 1ull << p.outer_bits;
+  const int root_step = p.n_tensors - 2;
+  for (uint64_t it = 0; it < n_it; ++it) {
+    if (!all && sel.find(it) == sel.end()) continue;
+    for (size_t i = p.n_phase0; i < p.sched.size(); ++i) {
+      tn_status s = run_step(c, p.sched[i], it, probe);
+      if (s != TN_OK) return s;
+    }
+    tnk::SumArgs sa;
+    memset(&sa, 0, sizeof sa);
+    if (p.n_tensors == 1) {
+      sa.root = static_cast<const float2*>(leaves[0]);
+    } else {
+      sa.root = reinterpret_cast<const float2*>(c.ws + p.steps[root_step].c_off);
+    }
+    sa.out = outp;
+    sa.open_bits = p.open_bits;
+    sa.res_bits = p.resident_bits;
+    sa.mode = out_mode;
+    copy_bits(sa.s_open, p.root_open_log2);
+    copy_bits(sa.s_res, p.root_res_log2);
+    for (int j = 0; j < p.resident_bits; ++j) sa.res_slicebit[j] = (int8_t)p.res_slicebit[j];
+    int64_t base = 0;
+    for (int j = 0; j < p.outer_bits; ++j) base |= (int64_t)((it >> j) & 1) << p.outer_slicebit[j];
+    sa.row_base = base;
+    if (all) {
+      sa.n_sel = -1;
+      hipLaunchKernelGGL(tnk::k_slice_sum, dim3(grid_for(n_out, 1u << 30)), dim3(tnk::kBlock), 0,
+                         st, sa);
+      TN_HIP_CHECK(hipGetLastError());
+    } else {
+      const auto& v = sel[it];
+      for (size_t i0 = 0; i0 < v.size(); i0 += tnk::kMaxSel) {
+        size_t cnt = std::min(v.size() - i0, (size_t)tnk::kMaxSel);
+        sa.n_sel = (int32_t)cnt;
+        for (size_t i = 0; i < cnt; ++i) {
+          sa.sel_r[i] = v[i0 + i].first;
+          sa.sel_row[i] = v[i0 + i].second;
+        }
+        hipLaunchKernelGGL(tnk::k_slice_sum, dim3(grid_for(n_out, 1u << 30)), dim3(tnk::kBlock),
+                           0, st, sa);
+        TN_HIP_CHECK(hipGetLastError());
+      }
+    }
+  }
+  return TN_OK;
+}
+
+extern "C" {
+
+tn_status tn_contract_backward(tn_plan_t plan, const void* const* leaves, const void* grad_out,
+                               void* const* grad_leaves, void* ws, size_t ws_bytes,
+                               void* stream) {
+  (void)plan;
+  (void)leaves;
+  (void)grad_out;
+  (void)grad_leaves;
+  (void)ws;
+  (void)ws_bytes;
+  (void)stream;
+  return fail(TN_E_UNSUPPORTED, "backward not built yet");
+}
+
+tn_status tn_permute(const void* in, void* out, int32_t nbits, const int8_t* in_log2,
+                     const int8_t* out_log2, void* stream) {
+  if (!in || !out || !in_log2 || !out_log2) return fail(TN_E_INVALID, "NULL argument");
+  if (nbits < 0 || nbits > 40) return fail(TN_E_INVALID, "nbits out of range");
+  uint64_t seen_in = 0, seen_out = 0;
+  for (int j = 0; j < nbits; ++j) {
+    if (in_log2[j] < 0 || in_log2[j] >= nbits || out_log2[j] < 0 || out_log2[j] >= nbits)
+      return fail(TN_E_INVALID, "stride outside the tensor");
+    seen_in |= 1ull << in_log2[j];
+    seen_out |= 1ull << out_log2[j];
+  }
+  uint64_t full = nbits == 64 ? ~0ull : ((1ull << nbits) - 1);
+  if (seen_in != full || seen_out != full) return fail(TN_E_INVALID, "strides are not a permutation");
+  tnk::PermArgs a;
+  memset(&a, 0, sizeof a);
+  a.in = static_cast<const float2*>(in);
+  a.out = static_cast<float2*>(out);
+  a.nbits = nbits;
+  for (int j = 0; j < nbits; ++j) {
+    a.sin[j] = in_log2[j];
+    a.sout[j] = out_log2[j];
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(tnk::k_permute_plain, dim3(grid_for(1ull << nbits)), dim3(tnk::kBlock), 0,
+                     st, a);
+  TN_HIP_CHECK(hipGetLastError());
+  return TN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,206 @@
+"""Plan (host side of the library) through the C ABI, on the CPU.
+
+* the library loads and exports every function include/tn.h declares;
+* malformed input is rejected with the documented status codes;
+* instance counts and multiply-add totals equal the brute-force enumeration
+  of named tasks over all slices (Sec. 3.2) done by the oracle;
+* executing the plan's own step descriptors on the CPU reproduces the
+  oracle's amplitude (layouts, folding of instances, arena offsets).
+"""
+
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import taskgraph, tn_oracle
+from tngen import circuits, network, path as tpath, slicing
+
+from paper_2107_09793_amd import binding
+from paper_2107_09793_amd.binding import Plan, TnError
+
+from .plan_exec import execute
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_library_exports_every_declared_function():
+    hdr = open(os.path.join(ROOT, "include", "tn.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    names = set(re.findall(r"\b(tn_[a-z_0-9]+)\s*\(", hdr))
+    assert {"tn_plan_create", "tn_contract", "tn_contract_backward"} <= names
+    L = binding.lib()
+    for nm in sorted(names):
+        assert hasattr(L, nm), nm
+    assert set(binding.EXPORTS) == names
+
+
+def _small_net(seed=0, rows=3, cols=4, depth=8, batch=None):
+    circ = circuits.grid_rqc(rows, cols, depth, seed=seed)
+    if batch:
+        b = circuits.random_bitstrings(circ.n, 2, batch, seed)
+        tn = network.relabel_compact(network.circuit_network(circ, batch=b))
+    else:
+        x = circuits.random_bitstrings(circ.n, 2, 1, seed)[0]
+        tn = network.relabel_compact(network.circuit_network(circ, outcome=x))
+    p = tpath.greedy_path(tn.labels, tn.dims, tn.open)
+    return tn, p
+
+
+def test_rejects_malformed_input():
+    tn, p = _small_net()
+    with pytest.raises(TnError) as e:
+        Plan(tn.labels, tn.dims, tn.open, p[:-1])
+    assert e.value.status == binding.TN_E_INVALID
+    bad = list(p)
+    bad[3] = (bad[3][0], bad[3][0])
+    with pytest.raises(TnError) as e:
+        Plan(tn.labels, tn.dims, tn.open, bad)
+    assert e.value.status == binding.TN_E_INVALID
+    dims = dict(tn.dims)
+    dims[0] = 3
+    with pytest.raises(TnError) as e:
+        Plan(tn.labels, dims, tn.open, p)
+    assert e.value.status == binding.TN_E_UNSUPPORTED
+    labels = [list(l) for l in tn.labels]
+    labels[5] = labels[5] + [labels[0][0]] if labels[0][0] not in labels[5] else labels[5]
+    with pytest.raises(TnError) as e:
+        Plan(labels, tn.dims, tn.open, p)
+    assert e.value.status == binding.TN_E_INVALID
+    with pytest.raises(TnError) as e:
+        Plan(tn.labels, tn.dims, tn.open, p, sliced=[10**6])
+    assert e.value.status == binding.TN_E_INVALID
+
+
+def _worked(D):
+    g = json.load(open(os.path.join(GOLD, "worked_example.json")))
+    names = g["leaf_order"]
+    letters = sorted({c for n in names for c in g["tensors"][n]})
+    ids = {c: i for i, c in enumerate(letters)}
+    labels = [[ids[c] for c in g["tensors"][n]] for n in names]
+    dims = {i: D for i in ids.values()}
+    return g, ids, labels, dims, [tuple(x) for x in g["path_ssa"]]
+
+
+@pytest.mark.parametrize("D", [2, 4])
+def test_worked_example_instances(D):
+    g, ids, labels, dims, path = _worked(D)
+    pl = Plan(labels, dims, [], path, sliced=[ids["e"]])
+    inst = [2 ** s["inst_bits"] for s in pl.steps()]
+    expect = [1 if c == 1 else D for c in g["instances_when_e_sliced"]]
+    assert inst == expect
+    info = pl.info()
+    # the printed orders D^p are the sizes of the steps' index sets
+    assert [len(s) for s in g["step_indices"]] == g["step_cost_power_of_D"]
+    # per slice, e is fixed: D^(|set| - [e in set]); with reuse each step
+    # additionally runs once per instance (Sec. 2.4 slicing overhead shows
+    # at step 6, which does not touch e unsliced but runs for both slices)
+    per_slice = [D ** (len(s) - ("e" in s)) for s in g["step_indices"]]
+    assert info["cmac_noreuse"] == pytest.approx(D * sum(per_slice))
+    assert info["cmac_reuse"] == pytest.approx(sum(i * c for i, c in zip(expect, per_slice)))
+
+
+@pytest.mark.parametrize("n_slice,batch", [(0, None), (3, None), (5, None), (2, 16)])
+def test_statistics_equal_task_enumeration(n_slice, batch):
+    tn, p = _small_net(seed=n_slice, batch=batch)
+    ts = slicing.TreeSets(tn.labels, tn.dims, tn.open, p)
+    sl = slicing.greedy_slices(ts, n_slice=n_slice) if n_slice else []
+    pl = Plan.from_network(tn, p, sl)
+    info = pl.info()
+    ref = taskgraph.enumerate_tasks(tn.labels, tn.dims, tn.open, p, sl)
+    assert info["cmac_reuse"] == pytest.approx(ref["flop_reuse"], rel=1e-12)
+    assert info["cmac_noreuse"] == pytest.approx(ref["flop_noreuse"], rel=1e-12)
+    assert info["cmac_per_slice"] == pytest.approx(ref["flop_sl"], rel=1e-12)
+    assert info["n_slices"] == ref["n_slices"]
+    # batch counts as instances too: the per-step instance count of the
+    # enumeration (slices only) times the batch carried by the step
+    steps = pl.steps()
+    for k, s in enumerate(steps):
+        assert 2 ** s["inst_bits"] == ref["instances"][k]
+    if n_slice:
+        f = taskgraph.shared_fraction(ref["flop_reuse"], ref["flop_sl"], ref["n_slices"])
+        assert info["f_sl"] == pytest.approx(f, rel=1e-12)
+
+
+@pytest.mark.parametrize("case", ["plain", "sliced3", "sliced6", "batch", "worked", "bosonic"])
+def test_cpu_execution_of_plan_matches_oracle(case):
+    rng = np.random.default_rng(1)
+    if case == "worked":
+        g, ids, labels, dims, path = _worked(2)
+        tensors = [rng.standard_normal([2] * len(l)) + 1j * rng.standard_normal([2] * len(l))
+                   for l in labels]
+        open_ids, sl = [], [ids["e"]]
+    else:
+        if case == "bosonic":
+            circ = circuits.gbs_like(2, 3, 2, seed=4, d=4)
+            x = circuits.random_bitstrings(circ.n, 4, 1, 4)[0]
+            tn = network.relabel_compact(network.circuit_network(circ, outcome=x))
+            path = tpath.greedy_path(tn.labels, tn.dims, tn.open)
+        else:
+            tn, path = _small_net(seed=2, batch=8 if case == "batch" else None)
+        labels, dims, tensors, open_ids = tn.labels, tn.dims, tn.tensors, tn.open
+        ns = {"plain": 0, "batch": 2, "sliced3": 3, "sliced6": 6, "bosonic": 2}[case]
+        ts = slicing.TreeSets(labels, dims, open_ids, path)
+        sl = slicing.greedy_slices(ts, n_slice=ns) if ns else []
+    pl = Plan(labels, dims, open_ids, path, sl)
+    got, per = execute(pl, tensors)
+    ref = tn_oracle.contract(tensors, labels, dims, open_ids, path, sl)
+    ref = np.asarray(ref).reshape(-1)
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-14 * np.max(np.abs(ref)))
+    if sl:
+        info = pl.info()
+        parts = tn_oracle.contract(tensors, labels, dims, open_ids, path, sl, per_slice=True)
+        parts = np.asarray(parts).reshape(parts.shape[0], -1)
+        # column r of the root holds slice id sum_j bit_j(r) << res_slicebit[j]
+        rb = info["n_resident_bits"]
+        for r in range(1 << rb):
+            sid = sum(((r >> j) & 1) << info["res_slicebit"][j] for j in range(rb))
+            assert np.allclose(per[:, r], parts[sid], rtol=1e-12, atol=1e-14)
+
+
+def test_liveness_never_overlaps_live_results():
+    tn, p = _small_net(seed=3, rows=4, cols=4, depth=8)
+    ts = slicing.TreeSets(tn.labels, tn.dims, tn.open, p)
+    sl = slicing.greedy_slices(ts, n_slice=3)
+    pl = Plan.from_network(tn, p, sl)
+    steps = pl.steps()
+    n = pl.n_tensors
+    order = [k for k in range(n - 1) if steps[k]["phase"] == 0] + \
+            [k for k in range(n - 1) if steps[k]["phase"] == 1]
+    pos = {k: i for i, k in enumerate(order)}
+    consumer = {}
+    for k, s in enumerate(steps):
+        consumer[s["a"]] = k
+        consumer[s["b"]] = k
+    live = []
+    for k in order:
+        s = steps[k]
+        end = pos[consumer[n + k]] if (n + k) in consumer else len(order)
+        live.append((pos[k], end, s["c_offset"], s["c_offset"] + s["c_bytes"]))
+    for i in range(len(live)):
+        for j in range(i + 1, len(live)):
+            a, b = live[i], live[j]
+            if a[0] <= b[1] and b[0] <= a[1]:      # lifetimes overlap
+                assert a[3] <= b[2] or b[3] <= a[2], (a, b)
+    info = pl.info()
+    assert info["arena_bytes"] <= info["bytes_no_deletion"]
+
+
+def test_outer_split_and_no_reuse_statistics():
+    tn, p = _small_net(seed=4, rows=4, cols=4, depth=10)
+    ts = slicing.TreeSets(tn.labels, tn.dims, tn.open, p)
+    sl = slicing.greedy_slices(ts, n_slice=4)
+    full = Plan.from_network(tn, p, sl).info()
+    assert full["n_outer_bits"] == 0 and full["n_resident_bits"] == 4
+    assert full["cmac_exec"] == pytest.approx(full["cmac_reuse"])
+    capped = Plan.from_network(tn, p, sl, max_resident_bits=2).info()
+    assert capped["n_resident_bits"] <= 2 and capped["n_outer_bits"] >= 2
+    assert capped["cmac_exec"] >= full["cmac_exec"]
+    assert capped["cmac_exec"] <= full["cmac_noreuse"] + 1e-6
+    nr = Plan.from_network(tn, p, sl, no_reuse=True).info()
+    assert nr["cmac_exec"] == pytest.approx(full["cmac_noreuse"])
+    lim = Plan.from_network(tn, p, sl, workspace_limit=full["arena_bytes"] // 3).info()
+    assert lim["arena_bytes"] <= full["arena_bytes"] // 3
