@@ -43,8 +43,8 @@ WORKLOAD_DESC = {
 
 def dominant_step(plan, leaves, info, steps, torch):
     """Step with the longest single execution among the heaviest candidates."""
-    cand = sorted(range(len(steps)), key=lambda k: -steps[k]["cmac"])[:6]
-    cand += sorted(range(len(steps)), key=lambda k: -steps[k]["bytes"])[:6]
+    cand = sorted(range(len(steps)), key=lambda k: -steps[k]["cmac"])[:3]
+    cand += sorted(range(len(steps)), key=lambda k: -steps[k]["bytes"])[:2]
     best, best_ms = None, -1.0
     for k in dict.fromkeys(cand):
         e0 = torch.cuda.Event(enable_timing=True)
@@ -70,6 +70,30 @@ def roofline(step, avg_s, precision):
     ach = 8.0 * step["cmac"] / avg_s / 1e12
     return dict(bound="alu", achieved=ach, peak=PEAKS["alu"], unit="TFLOP/s",
                 frac=ach / PEAKS["alu"])
+
+
+def measured_traffic(step, precision):
+    """HBM bytes of the dominant step from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the summary is
+    for another step shape or precision, or the GEMM source changed since."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_gemm_{precision}_sliced30q.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_b = re.search(r"traffic_bytes:\s*([0-9.eE+]+)", txt)
+    m_h = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
+    m_s = re.search(r"step_shape:\s*b(\d+) m(\d+) n(\d+) k(\d+)", txt)
+    if not (m_b and m_h and m_s):
+        return None
+    h = hashlib.sha256()
+    for f in ("paper_2107_09793_amd/csrc/kernels_gemm.h", "paper_2107_09793_amd/csrc/kernels_common.h"):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    shape = tuple(int(x) for x in m_s.groups())
+    if h.hexdigest()[:16] != m_h.group(1) or shape != (step["nb"], step["nm"], step["nn"], step["nk"]):
+        return None
+    return float(m_b.group(1))
 
 
 def cpu_baseline(w, n_sample, gpu_per_slice):
@@ -165,7 +189,8 @@ def main():
                amplitude=[float(out.real.item()), float(out.imag.item())] if out.numel() == 1 else None)
     d = steps[dom]
     rl = roofline(d, dom_s, args.precision)
-    rl.update(traffic=None, step=dom, kernel=d["kind_name"], cmac=d["cmac"],
+    rl.update(traffic=measured_traffic(d, args.precision), step=dom, kernel=d["kind_name"],
+              cmac=d["cmac"],
               bytes=d["bytes"], avg_ms=dom_s * 1e3,
               shape=dict(nb=d["nb"], nm=d["nm"], nn=d["nn"], nk=d["nk"]))
     rec["roofline"] = rl

@@ -62,13 +62,22 @@ typedef enum { TN_OUT_SUM = 0, TN_OUT_PER_SLICE = 1 } tn_out_mode;
 /* plan flags */
 #define TN_FLAG_NO_REUSE 1u   /* every slice recomputes every step (Eq. sliced_flops) */
 #define TN_FLAG_SIMPLE_KERNELS 2u /* force the plain per-element kernels (debug)     */
+#define TN_N_GEMM_CONFIGS 6       /* tile configurations per precision              */
 
 typedef struct {
   int32_t precision;          /* tn_precision                                       */
   int32_t max_resident_bits;  /* cap on log2(slices computed together); -1 = auto   */
   int64_t workspace_limit;    /* bytes the arena may use; 0 = no limit              */
   uint32_t flags;             /* TN_FLAG_*                                          */
-  int32_t reserved[7];
+  int32_t gemm_config;        /* -1: per step from the tune table / built-in rule;
+                                 >= 0: this tile configuration for every GEMM step  */
+  const int32_t* tune;        /* n_tune entries of 5 int32 {precision, nm, nn, nk,
+                                 config}: measured best tile configuration for GEMM
+                                 steps of that shape (log2 rows, cols, summed); a
+                                 step uses the entry of its precision and nn with
+                                 the nearest (nm, nk); copied at plan creation     */
+  int32_t n_tune;
+  int32_t reserved[5];
 } tn_plan_options;
 
 typedef struct {
@@ -109,6 +118,7 @@ typedef struct {
   int32_t kind;               /* kernel family chosen for the step                */
   int32_t nb, nm, nn, nk;     /* bits of batch / row / column / summed indices    */
   int32_t inst_bits;          /* log2 instances (slices) computed by this step    */
+  int32_t tile;               /* GEMM tile configuration (kind == GEMM)           */
   double cmac;                /* multiply-adds per execution                      */
   /* log2 strides (elements) of each bit, least significant index bit first;
    * A holds batch,m,k; B holds batch,k,n; C holds batch,m,n. */

@@ -1,0 +1,59 @@
+"""torch.autograd face of the library.
+
+``Amplitude.apply(plan, *leaves)`` returns the contraction (complex128) and,
+on backward, calls tn_contract_backward for the leaf gradients (PyTorch's
+convention for complex tensors: dL/dRe + i dL/dIm).  Gradients with respect
+to gate parameters follow from torch's chain rule through the differentiable
+leaf construction below.
+"""
+
+import torch
+
+
+class Amplitude(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, plan, *leaves):
+        ctx.plan = plan
+        ctx.save_for_backward(*leaves)
+        return plan.contract(list(leaves))
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        leaves = ctx.saved_tensors
+        grads = [torch.zeros_like(x) if ctx.needs_input_grad[i + 1] else None
+                 for i, x in enumerate(leaves)]
+        ctx.plan.backward(list(leaves), grad_out, grads)
+        return (None, *grads)
+
+
+def fsim(theta, phi):
+    """fSim(theta, phi) in the basis |00>,|01>,|10>,|11> as a complex64 tensor
+    of shape (2, 2, 2, 2) = [out_a, out_b, in_a, in_b], differentiable in
+    theta and phi (real float64 scalars)."""
+    c = torch.cos(theta)
+    s = torch.sin(theta)
+    zero = torch.zeros_like(c)
+    one = torch.ones_like(c)
+    re = torch.stack([one, zero, zero, zero,
+                      zero, c, zero, zero,
+                      zero, zero, c, zero,
+                      zero, zero, zero, torch.cos(phi)])
+    im = torch.stack([zero, zero, zero, zero,
+                      zero, zero, -s, zero,
+                      zero, -s, zero, zero,
+                      zero, zero, zero, -torch.sin(phi)])
+    return torch.complex(re, im).to(torch.complex64).reshape(2, 2, 2, 2)
+
+
+def circuit_leaves(tn, circuit, params, device):
+    """Leaves of a network built from a trainable circuit: every fSim leaf
+    with a parameter index is rebuilt from ``params`` (n_param x 2 float64
+    tensor, requires_grad for gradients); the other leaves are constants."""
+    out = []
+    for t, oi in zip(tn.tensors, tn.leaf_op):
+        op = circuit.ops[oi]
+        if op.param is not None and t.shape == (2, 2, 2, 2):
+            out.append(fsim(params[op.param, 0], params[op.param, 1]).to(device))
+        else:
+            out.append(torch.from_numpy(t.astype("complex64")).to(device))
+    return out

@@ -26,7 +26,8 @@ I8x48 = ctypes.c_int8 * 48
 class PlanOptions(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_resident_bits", ctypes.c_int32),
                 ("workspace_limit", ctypes.c_int64), ("flags", ctypes.c_uint32),
-                ("reserved", ctypes.c_int32 * 7)]
+                ("gemm_config", ctypes.c_int32), ("tune", ctypes.POINTER(ctypes.c_int32)),
+                ("n_tune", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -45,7 +46,7 @@ class PlanInfo(ctypes.Structure):
 
 class StepInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
-        "a", "b", "c", "phase", "kind", "nb", "nm", "nn", "nk", "inst_bits")] + \
+        "a", "b", "c", "phase", "kind", "nb", "nm", "nn", "nk", "inst_bits", "tile")] + \
         [("cmac", ctypes.c_double)] + \
         [(n, I8x48) for n in ("sA_b", "sB_b", "sC_b", "sA_m", "sC_m", "sB_n", "sC_n",
                               "sA_k", "sB_k")] + \
@@ -119,6 +120,19 @@ def _stream_ptr(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+TUNE_PATH = os.path.join(_HERE, "tune", "gfx950.json")
+
+
+def load_tune_table(path=TUNE_PATH):
+    """Autotuned GEMM tile choices: list of [precision, nm, nn, nk, config]."""
+    if not os.path.exists(path):
+        return []
+    import json
+    with open(path) as f:
+        doc = json.load(f)
+    return [list(map(int, e[:5])) for e in doc.get("entries", [])]
+
+
 class Plan:
     """A contraction plan (``tn_plan_create``).
 
@@ -128,7 +142,8 @@ class Plan:
     """
 
     def __init__(self, labels, dims, open_ids, path, sliced=(), precision="c64",
-                 max_resident_bits=-1, workspace_limit=0, no_reuse=False, simple=False):
+                 max_resident_bits=-1, workspace_limit=0, no_reuse=False, simple=False,
+                 gemm_config=-1, tune="default"):
         n_index = (max(dims) + 1) if isinstance(dims, dict) else len(dims)
         dim_arr = [dims[i] for i in range(n_index)]
         ranks, r_p = _i32([len(l) for l in labels])
@@ -142,6 +157,11 @@ class Plan:
         opts.max_resident_bits = max_resident_bits
         opts.workspace_limit = workspace_limit
         opts.flags = (TN_FLAG_NO_REUSE if no_reuse else 0) | (TN_FLAG_SIMPLE_KERNELS if simple else 0)
+        opts.gemm_config = gemm_config
+        entries = load_tune_table() if tune == "default" else (tune or [])
+        tarr, t_p = _i32([x for e in entries for x in e] or [0])
+        opts.tune = t_p
+        opts.n_tune = len(entries)
         h = ctypes.c_void_p()
         _check(lib().tn_plan_create(len(labels), r_p, ids_p, n_index, d_p, len(open_ids), op_p,
                                     len(path), pa_p, len(sliced), sl_p, ctypes.byref(opts),
@@ -240,6 +260,9 @@ class Plan:
             _check(lib().tn_contract(*args))
         else:
             step, e0, e1 = probe
+            for e in (e0, e1):
+                if not e.cuda_event:        # torch creates the HIP event on first record
+                    e.record()
             _check(lib().tn_contract_probe(*args, step, ctypes.c_void_p(e0.cuda_event),
                                            ctypes.c_void_p(e1.cuda_event)))
         return out

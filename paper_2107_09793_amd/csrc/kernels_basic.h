@@ -104,30 +104,82 @@ __global__ void __launch_bounds__(kBlock) k_splitk_reduce(StepArgs p, int64_t nc
 
 // ---------------------------------------------------------------------------
 // Stream: few summed and few column bits (nk <= 4, nn <= 4).  One thread per
-// row (b, m) keeps its 2^nk operand values in registers and produces its
-// 2^nn outputs; the small operand is read through the cache.
+// row r = (m, b) keeps its 2^nk operand values in registers and produces its
+// 2^nn outputs; the small operand is read through the cache.  Row offsets are
+// split into the lane's low 8 bits (computed once) and the workgroup's high
+// bits (uniform); every stride table is read at compile-time indices.
+struct StreamArgs {
+  const float2* A;
+  const float2* B;
+  float2* C;
+  int32_t nrow;           // row bits: m bits then batch bits
+  int32_t nbB;            // batch bits (the top nbB row bits), B's batch strides below
+  int32_t conjA, conjB, accumulate;
+  int8_t rowA[kMaxBits], rowC[kMaxBits];   // strides of row bit j in A and C
+  int8_t bB[kMaxBits];                     // stride in B of batch bit j
+  int8_t kA[4], kB[4], nB[4], nC[4];
+};
+
+template <int N>
+__device__ __forceinline__ int64_t scatter_c(uint64_t idx, const int8_t* s, int lo, int hi) {
+  int64_t off = 0;
+#pragma unroll
+  for (int j = 0; j < N; ++j)
+    if (j >= lo && j < hi) off += (int64_t)((idx >> j) & 1ull) << s[j];
+  return off;
+}
+
 template <int NK, int NN>
-__global__ void __launch_bounds__(kBlock) k_stream(StepArgs p) {
-  const uint64_t rows = 1ull << (p.nb + p.nm);
-  for (uint64_t r = (uint64_t)blockIdx.x * kBlock + threadIdx.x; r < rows;
-       r += (uint64_t)gridDim.x * kBlock) {
-    uint64_t m = r & ((1ull << p.nm) - 1);
-    uint64_t b = r >> p.nm;
-    int64_t oa = scatter(m, p.sA_m, p.nm) + scatter(b, p.sA_b, p.nb);
-    int64_t ob = scatter(b, p.sB_b, p.nb);
-    int64_t oc = scatter(m, p.sC_m, p.nm) + scatter(b, p.sC_b, p.nb);
+__global__ void __launch_bounds__(kBlock) k_stream(StreamArgs p) {
+  constexpr int KN = (1 << NK) * (1 << NN);
+  __shared__ float2 sB[KN];
+  const int nrow = p.nrow;
+  const uint64_t rows = 1ull << nrow;
+  const int low = nrow < 8 ? nrow : 8;
+  const int64_t la = scatter_c<8>(threadIdx.x, p.rowA, 0, low);
+  const int64_t lc = scatter_c<8>(threadIdx.x, p.rowC, 0, low);
+  int64_t kofA[1 << NK];
+#pragma unroll
+  for (int k = 0; k < (1 << NK); ++k) kofA[k] = scatter_c<NK>(k, p.kA, 0, NK);
+  const int brow0 = nrow - p.nbB;   // first batch bit among the row bits
+  // B lives in LDS when all rows of a workgroup pass share one batch value
+  const bool shared_b = p.nbB == 0 || brow0 >= 8;
+  int64_t staged = -1;
+  for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < rows;
+       base += (uint64_t)gridDim.x * kBlock) {
+    const int64_t ha = scatter_c<kMaxBits>(base, p.rowA, 8, nrow);   // uniform
+    const int64_t hc = scatter_c<kMaxBits>(base, p.rowC, 8, nrow);
+    if (shared_b) {
+      const int64_t ob = p.nbB ? scatter_c<kMaxBits>(base >> brow0, p.bB, 0, p.nbB) : 0;
+      if (ob != staged) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < KN; i += kBlock) {
+          const int k = i / (1 << NN), n = i % (1 << NN);
+          sB[i] = maybe_conj(p.B[ob + scatter_c<NK>(k, p.kB, 0, NK) + scatter_c<NN>(n, p.nB, 0, NN)],
+                             p.conjB);
+        }
+        __syncthreads();
+        staged = ob;
+      }
+    }
+    const uint64_t r = base + threadIdx.x;
+    if (r >= rows) continue;
+    const int64_t oa = la + ha, oc = lc + hc;
     float2 a[1 << NK];
 #pragma unroll
-    for (int k = 0; k < (1 << NK); ++k)
-      a[k] = maybe_conj(p.A[oa + scatter(k, p.sA_k, NK)], p.conjA);
+    for (int k = 0; k < (1 << NK); ++k) a[k] = maybe_conj(p.A[oa + kofA[k]], p.conjA);
+    const int64_t ob = shared_b ? 0 : scatter_c<kMaxBits>(r >> brow0, p.bB, 0, p.nbB);
 #pragma unroll
     for (int n = 0; n < (1 << NN); ++n) {
-      int64_t obn = ob + scatter(n, p.sB_n, NN);
       float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
-      for (int k = 0; k < (1 << NK); ++k)
-        cfma(acc, a[k], maybe_conj(p.B[obn + scatter(k, p.sB_k, NK)], p.conjB));
-      int64_t ocn = oc + scatter(n, p.sC_n, NN);
+      for (int k = 0; k < (1 << NK); ++k) {
+        float2 b = shared_b ? sB[k * (1 << NN) + n]
+                            : maybe_conj(p.B[ob + scatter_c<NK>(k, p.kB, 0, NK) +
+                                             scatter_c<NN>(n, p.nB, 0, NN)], p.conjB);
+        cfma(acc, a[k], b);
+      }
+      const int64_t ocn = oc + scatter_c<NN>(n, p.nC, 0, NN);
       if (p.accumulate) {
         float2 c = p.C[ocn];
         acc.x += c.x;
@@ -219,6 +271,33 @@ __global__ void __launch_bounds__(kBlock) k_slice_sum(SumArgs p) {
         p.out[(int64_t)p.sel_row[i] * (int64_t)n_out + o] = make_double2(v.x, v.y);
       }
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of the slice sum: every resident slice of the root receives the
+// output gradient of its output element.
+struct RootGradArgs {
+  const double2* grad_out;
+  float2* dst;
+  int32_t open_bits, res_bits, accumulate;
+  int8_t s_open[kMaxBits], s_res[kMaxBits];
+};
+
+__global__ void __launch_bounds__(kBlock) k_root_grad(RootGradArgs p) {
+  const uint64_t n = 1ull << (p.open_bits + p.res_bits);
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * kBlock) {
+    uint64_t o = i & ((1ull << p.open_bits) - 1), r = i >> p.open_bits;
+    int64_t off = scatter(o, p.s_open, p.open_bits) + scatter(r, p.s_res, p.res_bits);
+    double2 g = p.grad_out[o];
+    float2 v = make_float2((float)g.x, (float)g.y);
+    if (p.accumulate) {
+      float2 c = p.dst[off];
+      v.x += c.x;
+      v.y += c.y;
+    }
+    p.dst[off] = v;
   }
 }
 

@@ -1,0 +1,427 @@
+// Complex GEMM steps on the matrix cores (MFMA), with operands read in
+// place through their bit strides (no separate transpose pass).
+//
+// Complex arithmetic as one real GEMM: with A row-major and complex
+// interleaved, A is a real M x 2K matrix; B becomes the real 2K x 2N matrix
+//   [[ Br, Bi], [-Bi, Br]]  per complex entry,
+// so the real product is C in interleaved form.  On the FP32 matrix path one
+// v_mfma_f32_32x32x2f32 covers one complex k for a 32 x 16 complex block:
+// lanes 0-31 carry Re A / the first row of the 2x2 block of B, lanes 32-63
+// Im A / the second row.
+//
+// Split-BF16 path: every float x = hi + lo with hi = bf16(x), lo = bf16(x - hi)
+// (round to nearest even); a product is hi*hi + hi*lo + lo*hi with float32
+// accumulation (the lo*lo term, ~2^-16 relative, is dropped).  One
+// v_mfma_f32_32x32x16_bf16 covers 8 complex k for a 32 x 16 complex block.
+//
+// Tiles: a workgroup of 256 threads (2 x 2 or 4 x 1 waves) owns an MT x NT
+// complex output tile and walks k in tiles of KT through double-buffered
+// LDS.  At start the workgroup tabulates in LDS the in-tile offsets of rows,
+// columns and k of every operand (one bit scatter per entry); afterwards all
+// addressing is table lookups and adds.  A tile's elements are enumerated in
+// (approximately) increasing stride order so consecutive lanes touch
+// consecutive addresses whenever the layout allows.  Workgroup ids are
+// remapped so that the tiles one XCD (one L2) runs share their A rows.
+#pragma once
+
+#include "kernels_common.h"
+
+namespace tnk {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
+struct GemmArgs {
+  StepArgs s;
+  // Enumeration of a tile's elements: bit j of the element index is a row
+  // (A) / column (B) bit if bit j of the mask is set, else a k bit; bits of
+  // one class keep their class order.
+  uint32_t a_mask, b_mask;
+  int32_t xcd_remap;
+};
+
+template <int V>
+struct ilog2 {
+  static constexpr int value = 1 + ilog2<V / 2>::value;
+};
+template <>
+struct ilog2<1> {
+  static constexpr int value = 0;
+};
+
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ uint32_t pack2(uint16_t lo16, uint16_t hi16) {
+  return (uint32_t)lo16 | ((uint32_t)hi16 << 16);
+}
+
+// Split element index e into (class-1 index, class-2 index) by mask.
+__device__ __forceinline__ void split_bits(int e, uint32_t mask, int nbits, int& i1, int& i2) {
+  int c1 = 0, c2 = 0;
+  i1 = 0;
+  i2 = 0;
+  for (int j = 0; j < nbits; ++j) {
+    int bit = (e >> j) & 1;
+    if ((mask >> j) & 1u) { i1 |= bit << c1; ++c1; } else { i2 |= bit << c2; ++c2; }
+  }
+}
+
+// Offsets shared by both precisions.
+template <int MT, int NT, int KT>
+struct GemmTables {
+  int64_t am[MT], ak[KT], bk[KT], bn[NT], cm[MT], cn[NT];
+};
+
+template <int MT, int NT, int KT>
+__device__ __forceinline__ void build_tables(const StepArgs& p, GemmTables<MT, NT, KT>& t) {
+  constexpr int LM = ilog2<MT>::value, LN = ilog2<NT>::value, LK = ilog2<KT>::value;
+  const int tid = threadIdx.x;
+  const int nmv = p.nm < LM ? p.nm : LM, nnv = p.nn < LN ? p.nn : LN, nkv = p.nk < LK ? p.nk : LK;
+  for (int i = tid; i < MT; i += 256) {
+    t.am[i] = scatter(i, p.sA_m, nmv);
+    t.cm[i] = scatter(i, p.sC_m, nmv);
+  }
+  for (int i = tid; i < NT; i += 256) {
+    t.bn[i] = scatter(i, p.sB_n, nnv);
+    t.cn[i] = scatter(i, p.sC_n, nnv);
+  }
+  for (int i = tid; i < KT; i += 256) {
+    t.ak[i] = scatter(i, p.sA_k, nkv);
+    t.bk[i] = scatter(i, p.sB_k, nkv);
+  }
+}
+
+// Coordinates (batch, row tile, column tile) of logical tile t; with the
+// remap, tile t runs on XCD t % 8 and each XCD walks a contiguous range of
+// tiles (column tiles fastest), so the tiles resident on one L2 share rows of A.
+__device__ __forceinline__ void tile_coords(const StepArgs& p, int LM, int LN, uint64_t t,
+                                            uint64_t ntiles, int remap, uint64_t& bidx,
+                                            uint64_t& mt, uint64_t& nt) {
+  if (remap) t = (t & 7) * (ntiles >> 3) + (t >> 3);
+  int lnt = p.nn > LN ? p.nn - LN : 0;
+  int lmt = p.nm > LM ? p.nm - LM : 0;
+  nt = t & ((1ull << lnt) - 1);
+  mt = (t >> lnt) & ((1ull << lmt) - 1);
+  bidx = t >> (lnt + lmt);
+}
+
+// Everything both GEMM kernels share: tables, tile bases, per-thread element
+// offsets (independent of the tile), the Gray-code walk over k tiles, and the
+// epilogue.  One workgroup per output tile.
+template <int MT, int NT, int KT, class OffT>
+struct GemmCommon {
+  static constexpr int LM = ilog2<MT>::value, LN = ilog2<NT>::value, LK = ilog2<KT>::value;
+  static constexpr int AE = MT * KT / 256, BE = NT * KT / 256;
+  int64_t baseA, baseB, baseC, kA, kB;
+  uint64_t gray, nkt, ntiles, tile;
+  OffT a_go[AE], b_go[BE];   // in-tile offsets (32-bit when they fit)
+  int a_mk[AE], b_nk[BE];    // packed LDS coordinates: row/col | k << 16
+  uint32_t a_ok, b_ok;
+  int remap;
+
+  __device__ __forceinline__ void init(const GemmArgs& g, const GemmTables<MT, NT, KT>& t) {
+    const StepArgs& p = g.s;
+    const int tid = threadIdx.x;
+    const int mlim = 1 << (p.nm < LM ? p.nm : LM), nlim = 1 << (p.nn < LN ? p.nn : LN);
+    const int klim = 1 << (p.nk < LK ? p.nk : LK);
+    a_ok = 0;
+    b_ok = 0;
+#pragma unroll
+    for (int r = 0; r < AE; ++r) {
+      int mi, ki;
+      split_bits(tid + 256 * r, g.a_mask, LM + LK, mi, ki);
+      a_mk[r] = mi | (ki << 16);
+      a_go[r] = (OffT)(t.am[mi] + t.ak[ki]);
+      if (mi < mlim && ki < klim) a_ok |= 1u << r;
+    }
+#pragma unroll
+    for (int r = 0; r < BE; ++r) {
+      int ni, ki;
+      split_bits(tid + 256 * r, g.b_mask, LN + LK, ni, ki);
+      b_nk[r] = ni | (ki << 16);
+      b_go[r] = (OffT)(t.bn[ni] + t.bk[ki]);
+      if (ni < nlim && ki < klim) b_ok |= 1u << r;
+    }
+    nkt = 1ull << (p.nk > LK ? p.nk - LK : 0);
+    int lnt = p.nn > LN ? p.nn - LN : 0;
+    int lmt = p.nm > LM ? p.nm - LM : 0;
+    ntiles = 1ull << (p.nb + lmt + lnt);
+    remap = g.xcd_remap;
+    tile = blockIdx.x;
+  }
+
+  __device__ __forceinline__ void set_tile(const StepArgs& p, uint64_t t) {
+    uint64_t bidx, mt, nt;
+    tile_coords(p, LM, LN, t, ntiles, remap, bidx, mt, nt);
+    baseA = scatter_range(mt << LM, p.sA_m, LM, p.nm) + scatter(bidx, p.sA_b, p.nb);
+    baseB = scatter_range(nt << LN, p.sB_n, LN, p.nn) + scatter(bidx, p.sB_b, p.nb);
+    baseC = scatter_range(mt << LM, p.sC_m, LM, p.nm) + scatter_range(nt << LN, p.sC_n, LN, p.nn) +
+            scatter(bidx, p.sC_b, p.nb);
+    kA = kB = 0;
+    gray = 0;
+  }
+
+  __device__ __forceinline__ void advance(const StepArgs& p, uint64_t kt) {
+    int j = __builtin_ctzll(kt);
+    uint64_t bit = 1ull << j;
+    int64_t da = (int64_t)1 << p.sA_k[LK + j], db = (int64_t)1 << p.sB_k[LK + j];
+    if (gray & bit) { kA -= da; kB -= db; } else { kA += da; kB += db; }
+    gray ^= bit;
+  }
+
+  __device__ __forceinline__ void gload(const StepArgs& p, float2* ra, float2* rb) {
+#pragma unroll
+    for (int r = 0; r < AE; ++r)
+      ra[r] = (a_ok >> r) & 1u ? p.A[baseA + kA + a_go[r]] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int r = 0; r < BE; ++r)
+      rb[r] = (b_ok >> r) & 1u ? p.B[baseB + kB + b_go[r]] : make_float2(0.f, 0.f);
+  }
+
+  // lane holds real column (lane & 31) of each 32x32 block, rows
+  // 8*(r/4) + 4*(lane/32) + r%4 for accumulator r
+  template <int WVN, int WM, int WN>
+  __device__ __forceinline__ void epilogue(const StepArgs& p, const GemmTables<MT, NT, KT>& t,
+                                           int64_t cbase, floatx16 (&acc)[WM][WN]) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wave_m = wave / WVN, wave_n = wave % WVN;
+    const int half = lane >> 5, par = lane & 1;
+    const int mlim = 1 << (p.nm < LM ? p.nm : LM), nlim = 1 << (p.nn < LN ? p.nn : LN);
+    float* C = reinterpret_cast<float*>(p.C + cbase);
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      int col = wave_n * WN * 16 + j * 16 + ((lane & 31) >> 1);
+      if (col >= nlim) continue;
+      int64_t offn = t.cn[col];
+#pragma unroll
+      for (int i = 0; i < WM; ++i) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          int row = wave_m * WM * 32 + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+          if (row >= mlim) continue;
+          float* cf = C + 2 * (offn + t.cm[row]) + par;
+          float v = acc[i][j][r];
+          if (p.accumulate) v += *cf;
+          *cf = v;
+        }
+      }
+    }
+  }
+};
+
+// The persistent tile loop shared by both precisions.  OPS supplies the LDS
+// staging (lstore) and the MFMA block for one k tile (compute).
+template <int WVN, int WM, int WN, int MT, int NT, int KT, class OffT, class Ops>
+__device__ __forceinline__ void gemm_tiles(const StepArgs& p, GemmCommon<MT, NT, KT, OffT>& c,
+                                           const GemmTables<MT, NT, KT>& tab, Ops& ops) {
+  using GC = GemmCommon<MT, NT, KT, OffT>;
+  float2 ra[GC::AE], rb[GC::BE];
+  if (c.tile >= c.ntiles) return;
+  c.set_tile(p, c.tile);
+  c.gload(p, ra, rb);
+  floatx16 acc[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+  ops.lstore(0, ra, rb);
+  __syncthreads();
+  for (uint64_t kt = 0; kt < c.nkt; ++kt) {
+    const int buf = kt & 1;
+    const bool last = kt + 1 == c.nkt;
+    if (!last) {
+      c.advance(p, kt + 1);
+      c.gload(p, ra, rb);
+    }
+    ops.compute(buf, acc);
+    if (!last) ops.lstore(buf ^ 1, ra, rb);
+    __syncthreads();
+  }
+  c.template epilogue<WVN, WM, WN>(p, tab, c.baseC, acc);
+}
+
+// ---------------------------------------------------------------------------
+// complex64 on FP32 MFMA
+template <int WVM, int WVN, int WM, int WN, int MT, int NT, int KT, class GC>
+struct OpsC64 {
+  float (*sA)[2][KT][MT];
+  float2 (*sB)[KT][NT];
+  const GC* c;
+  float sa, sb;
+  int lane, wave_m, wave_n;
+  __device__ __forceinline__ void lstore(int buf, const float2* ra, const float2* rb) {
+#pragma unroll
+    for (int r = 0; r < GC::AE; ++r) {
+      const int m = c->a_mk[r] & 0xFFFF, k = c->a_mk[r] >> 16;
+      sA[buf][0][k][m] = ra[r].x;
+      sA[buf][1][k][m] = sa * ra[r].y;
+    }
+#pragma unroll
+    for (int r = 0; r < GC::BE; ++r)
+      sB[buf][c->b_nk[r] >> 16][c->b_nk[r] & 0xFFFF] = make_float2(rb[r].x, sb * rb[r].y);
+  }
+  __device__ __forceinline__ void compute(int buf, floatx16 (&acc)[WM][WN]) {
+    const int half = lane >> 5, par = lane & 1;
+#pragma unroll 4
+    for (int kk = 0; kk < KT; ++kk) {
+      float av[WM], bv[WN];
+#pragma unroll
+      for (int i = 0; i < WM; ++i) av[i] = sA[buf][half][kk][wave_m * WM * 32 + i * 32 + (lane & 31)];
+#pragma unroll
+      for (int j = 0; j < WN; ++j) {
+        float2 bc = sB[buf][kk][wave_n * WN * 16 + j * 16 + ((lane & 31) >> 1)];
+        bv[j] = half == 0 ? (par ? bc.y : bc.x) : (par ? bc.x : -bc.y);
+      }
+#pragma unroll
+      for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+  }
+};
+
+template <int WVM, int WVN, int WM, int WN, int LK, class OffT>
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(LK == 4 && WVM * WM <= 4 && WVM * WM * WVN * WN <= 16 ? 3 : 1)))
+k_gemm_c64(GemmArgs g) {
+  constexpr int MT = WVM * WM * 32, NT = WVN * WN * 16, KT = 1 << LK;
+  using GC = GemmCommon<MT, NT, KT, OffT>;
+  static_assert(GC::AE >= 1 && GC::BE >= 1, "tile too small for 256 threads");
+  __shared__ float sA[2][2][KT][MT];
+  __shared__ float2 sB[2][KT][NT];
+  __shared__ GemmTables<MT, NT, KT> tab;
+  const StepArgs& p = g.s;
+  build_tables<MT, NT, KT>(p, tab);
+  __syncthreads();
+  GC c;
+  c.init(g, tab);
+  OpsC64<WVM, WVN, WM, WN, MT, NT, KT, GC> ops;
+  ops.sA = sA;
+  ops.sB = sB;
+  ops.c = &c;
+  ops.sa = p.conjA ? -1.f : 1.f;
+  ops.sb = p.conjB ? -1.f : 1.f;
+  ops.lane = threadIdx.x & 63;
+  ops.wave_m = (threadIdx.x >> 6) / WVN;
+  ops.wave_n = (threadIdx.x >> 6) % WVN;
+  gemm_tiles<WVN, WM, WN>(p, c, tab, ops);
+}
+
+// ---------------------------------------------------------------------------
+// split-BF16 (3 products) on BF16 MFMA with float32 accumulation.  LDS holds
+// the tile already split: A as [m][kr] and the real-embedded B as
+// [real column][kr] (kr = 2 kc + part), hi and lo planes.  Rows are 64 bytes;
+// the 16-byte chunk of a row is XOR-swizzled with bits 2-3 of the row so the
+// 16 lanes of one ds_read_b128 phase hit 16 distinct bank groups.  The split
+// uses the hardware round-to-nearest-even conversion (v_cvt_pk_bf16_f32).
+__device__ __forceinline__ int swz(int row, int kr) {
+  return row * 32 + ((((kr >> 3) ^ (row >> 2)) & 3) << 3) + (kr & 7);
+}
+
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef __bf16 b2v __attribute__((ext_vector_type(2)));
+
+// (x, y) -> packed bf16 hi pair and lo pair
+__device__ __forceinline__ void split_pair(float x, float y, uint32_t& hi, uint32_t& lo) {
+  f2v v = {x, y};
+  b2v h = __builtin_convertvector(v, b2v);
+  f2v hf = __builtin_convertvector(h, f2v);
+  b2v l = __builtin_convertvector(v - hf, b2v);
+  hi = __builtin_bit_cast(uint32_t, h);
+  lo = __builtin_bit_cast(uint32_t, l);
+}
+
+template <int WVM, int WVN, int WM, int WN, int MT, int NT, int KT, class GC>
+struct OpsSB16 {
+  uint16_t (*sA)[2][MT * 32];
+  uint16_t (*sB)[2][2 * NT * 32];
+  const GC* c;
+  uint32_t ca, cb;   // sign masks for the imaginary half (conjugation)
+  int lane, wave_m, wave_n;
+  __device__ __forceinline__ void lstore(int buf, const float2* ra, const float2* rb) {
+#pragma unroll
+    for (int r = 0; r < GC::AE; ++r) {
+      uint32_t hi, lo;
+      split_pair(ra[r].x, ra[r].y, hi, lo);
+      int o = swz(c->a_mk[r] & 0xFFFF, 2 * (c->a_mk[r] >> 16));
+      *reinterpret_cast<uint32_t*>(&sA[buf][0][o]) = hi ^ ca;
+      *reinterpret_cast<uint32_t*>(&sA[buf][1][o]) = lo ^ ca;
+    }
+#pragma unroll
+    for (int r = 0; r < GC::BE; ++r) {
+      uint32_t hi, lo;
+      split_pair(rb[r].x, rb[r].y, hi, lo);   // (Br, Bi) halves, conj applied below
+      hi ^= cb;
+      lo ^= cb;
+      int o = swz(2 * (c->b_nk[r] & 0xFFFF), 2 * (c->b_nk[r] >> 16));
+      // real column 2n: (Br, -Bi); real column 2n+1: (Bi, Br)
+      *reinterpret_cast<uint32_t*>(&sB[buf][0][o]) = hi ^ 0x80000000u;
+      *reinterpret_cast<uint32_t*>(&sB[buf][1][o]) = lo ^ 0x80000000u;
+      *reinterpret_cast<uint32_t*>(&sB[buf][0][o + 32]) = (hi >> 16) | (hi << 16);
+      *reinterpret_cast<uint32_t*>(&sB[buf][1][o + 32]) = (lo >> 16) | (lo << 16);
+    }
+  }
+  __device__ __forceinline__ void compute(int buf, floatx16 (&acc)[WM][WN]) {
+    const int half = lane >> 5;
+#pragma unroll
+    for (int s2 = 0; s2 < KT / 8; ++s2) {
+      const int kof = 16 * s2 + 8 * half;
+      bf16x8_t ah[WM], al[WM], bh[WN], bl[WN];
+#pragma unroll
+      for (int i = 0; i < WM; ++i) {
+        int row = wave_m * WM * 32 + i * 32 + (lane & 31);
+        ah[i] = *reinterpret_cast<const bf16x8_t*>(&sA[buf][0][swz(row, kof)]);
+        al[i] = *reinterpret_cast<const bf16x8_t*>(&sA[buf][1][swz(row, kof)]);
+      }
+#pragma unroll
+      for (int j = 0; j < WN; ++j) {
+        int col = wave_n * WN * 32 + j * 32 + (lane & 31);
+        bh[j] = *reinterpret_cast<const bf16x8_t*>(&sB[buf][0][swz(col, kof)]);
+        bl[j] = *reinterpret_cast<const bf16x8_t*>(&sB[buf][1][swz(col, kof)]);
+      }
+#pragma unroll
+      for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+        }
+    }
+  }
+};
+
+template <int WVM, int WVN, int WM, int WN, class OffT>
+__global__ void __launch_bounds__(256) k_gemm_sb16(GemmArgs g) {
+  constexpr int KT = 16;
+  constexpr int MT = WVM * WM * 32, NT = WVN * WN * 16;
+  using GC = GemmCommon<MT, NT, KT, OffT>;
+  static_assert(2 * KT == 32, "row layout assumes 32 bf16 per row");
+  __shared__ __attribute__((aligned(16))) uint16_t sA[2][2][MT * 32];
+  __shared__ __attribute__((aligned(16))) uint16_t sB[2][2][2 * NT * 32];
+  __shared__ GemmTables<MT, NT, KT> tab;
+  const StepArgs& p = g.s;
+  build_tables<MT, NT, KT>(p, tab);
+  __syncthreads();
+  GC c;
+  c.init(g, tab);
+  OpsSB16<WVM, WVN, WM, WN, MT, NT, KT, GC> ops;
+  ops.sA = sA;
+  ops.sB = sB;
+  ops.c = &c;
+  ops.ca = p.conjA ? 0x80000000u : 0u;
+  ops.cb = p.conjB ? 0x80000000u : 0u;
+  ops.lane = threadIdx.x & 63;
+  ops.wave_m = (threadIdx.x >> 6) / WVN;
+  ops.wave_n = (threadIdx.x >> 6) % WVN;
+  gemm_tiles<WVN, WM, WN>(p, c, tab, ops);
+}
+
+}  // namespace tnk

@@ -106,9 +106,10 @@ struct Layout {  // executed bits of a node with strides (bit id -> log2 stride)
 
 }  // namespace
 
-// Kernel family for a step of the given shape.
-static int32_t choose_kind(int nb, int nm, int nn, int nk, uint32_t flags, int32_t* chunks,
-                           int64_t* scratch) {
+// Kernel family for a step of the given shape (bit counts of the batch, row,
+// column and summed classes).
+int32_t choose_kind(int nb, int nm, int nn, int nk, uint32_t flags, int32_t* chunks,
+                    int64_t* scratch) {
   int out_bits = nb + nm + nn;
   *chunks = 0;
   *scratch = 0;
@@ -121,7 +122,26 @@ static int32_t choose_kind(int nb, int nm, int nn, int nk, uint32_t flags, int32
   }
   if (flags & 2u) return KIND_SIMPLE;
   if (nk <= 4 && nn <= 4 && nb <= 12) return KIND_STREAM;
+  if (nm >= 5 && nn >= 3 && nk >= 3) return KIND_GEMM;
   return KIND_SIMPLE;
+}
+
+int32_t choose_tile(const Plan& p, int nm, int nn, int nk) {
+  if (p.gemm_config >= 0) return p.gemm_config;
+  int best = -1, best_d = 1 << 30;
+  for (size_t i = 0; i + 4 < p.tune.size(); i += 5) {
+    const int32_t* e = &p.tune[i];
+    if (e[0] != p.precision || e[2] != nn || e[4] < 0 || e[4] >= kNumGemmConfigs) continue;
+    int d = std::abs(e[1] - nm) + 4 * std::abs(e[3] - nk);
+    if (d < best_d) {
+      best_d = d;
+      best = e[4];
+    }
+  }
+  if (best >= 0) return best;
+  if (nn >= 6) return 0;   // 128 x 64
+  if (nn == 5) return 1;   // 128 x 32
+  return 2;                // 256 x 16
 }
 
 // Build schedule for a given outer set; fills steps, sched, memory, stats.
@@ -185,10 +205,16 @@ static void schedule(Plan& p) {
     N = by(N, lay[b]);
     batch = by(batch, lay[a]);
     K = by(K, lay[a]);
-    // result layout, least significant first: columns, rows, batch
+    int nb = (int)batch.size(), nm = (int)M.size(), nnb = (int)N.size(), nk = (int)K.size();
+    S.kind = choose_kind(nb, nm, nnb, nk, p.flags, &S.splitk_chunks, &S.scratch_bytes);
+    // result layout, least significant first.  GEMM tiles store 16 consecutive
+    // columns per half-wave: columns, rows, batch.  The stream kernel runs one
+    // row per lane: rows, columns, batch.
     Bits clayout;
-    clayout.insert(clayout.end(), N.begin(), N.end());
-    clayout.insert(clayout.end(), M.begin(), M.end());
+    const Bits& lo = S.kind == KIND_STREAM ? M : N;
+    const Bits& mid = S.kind == KIND_STREAM ? N : M;
+    clayout.insert(clayout.end(), lo.begin(), lo.end());
+    clayout.insert(clayout.end(), mid.begin(), mid.end());
     clayout.insert(clayout.end(), batch.begin(), batch.end());
     for (size_t i = 0; i < clayout.size(); ++i) lay[v].s[clayout[i]] = (int8_t)i;
     p.node_layout[v] = clayout;
@@ -207,10 +233,9 @@ static void schedule(Plan& p) {
     fill(N, lay[v], S.nC);
     fill(K, lay[a], S.kA);
     fill(K, lay[b], S.kB);
-    int nb = (int)batch.size(), nm = (int)M.size(), nnb = (int)N.size(), nk = (int)K.size();
     S.cmac = std::ldexp(1.0, nb + nm + nnb + nk);
     S.c_bytes = (int64_t)8 << (nb + nm + nnb);
-    S.kind = choose_kind(nb, nm, nnb, nk, p.flags, &S.splitk_chunks, &S.scratch_bytes);
+    S.tile = S.kind == KIND_GEMM ? choose_tile(p, nm, nnb, nk) : -1;
     // instance bits all-resident: sliced bits of the operands
     Bits u = unite(p.node_bits[a], p.node_bits[b]);
     int sv = 0;
@@ -345,8 +370,13 @@ std::string build_plan(Plan& p, int32_t n_tensors, const int32_t* ranks,
                        int32_t n_open, const int32_t* open_ids, int32_t n_steps,
                        const int32_t* path, int32_t n_sliced, const int32_t* sliced_ids,
                        int32_t precision, int32_t max_resident_bits, int64_t ws_limit,
-                       uint32_t flags, bool* unsupported) {
+                       uint32_t flags, int32_t gemm_config, const int32_t* tune, int32_t n_tune,
+                       bool* unsupported) {
   *unsupported = false;
+  if (gemm_config >= kNumGemmConfigs) return "gemm_config out of range";
+  if (n_tune < 0 || (n_tune > 0 && !tune)) return "bad tune table";
+  p.gemm_config = gemm_config < 0 ? -1 : gemm_config;
+  p.tune.assign(tune, tune + 5 * (int64_t)n_tune);
   char buf[256];
   if (n_tensors < 1) return "n_tensors must be >= 1";
   if (n_index < 0 || n_open < 0 || n_sliced < 0) return "negative count";

@@ -31,6 +31,7 @@ struct StepDesc {
   int64_t c_bytes;
   int64_t scratch_bytes;  // split-k partials
   int32_t splitk_chunks;
+  int32_t tile;           // GEMM tile configuration
 };
 
 struct LeafDesc {
@@ -49,6 +50,8 @@ struct Plan {
   std::vector<int32_t> path;       // 2 * n_steps
   int32_t precision = PREC_C64;
   uint32_t flags = 0;
+  int32_t gemm_config = -1;
+  std::vector<int32_t> tune;       // 5 ints per entry
 
   // derived
   int32_t n_bits = 0;                        // global bits
@@ -91,6 +94,14 @@ struct Plan {
   int32_t n_launches = 0;
 };
 
+// Kernel family for a step shape; split-k chunk count and scratch bytes.
+int32_t choose_kind(int nb, int nm, int nn, int nk, uint32_t flags, int32_t* chunks,
+                    int64_t* scratch);
+
+// GEMM tile configuration for a step shape: forced, tune table, or rule.
+constexpr int kNumGemmConfigs = 6;
+int32_t choose_tile(const Plan& p, int nm, int nn, int nk);
+
 // Builds the plan; returns empty string on success, else an error message.
 // *unsupported is set when the input is valid but outside what is supported.
 std::string build_plan(Plan& p, int32_t n_tensors, const int32_t* ranks,
@@ -98,6 +109,7 @@ std::string build_plan(Plan& p, int32_t n_tensors, const int32_t* ranks,
                        int32_t n_open, const int32_t* open_ids, int32_t n_steps,
                        const int32_t* path, int32_t n_sliced, const int32_t* sliced_ids,
                        int32_t precision, int32_t max_resident_bits, int64_t ws_limit,
-                       uint32_t flags, bool* unsupported);
+                       uint32_t flags, int32_t gemm_config, const int32_t* tune, int32_t n_tune,
+                       bool* unsupported);
 
 }  // namespace tn

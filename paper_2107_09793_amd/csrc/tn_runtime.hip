@@ -6,6 +6,7 @@
 // resident slice results are added in float64 (Eq. sliced_sum).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -15,6 +16,7 @@
 
 #include "../../include/tn.h"
 #include "kernels_basic.h"
+#include "kernels_gemm.h"
 #include "plan.h"
 
 struct tn_plan_s {
@@ -68,25 +70,137 @@ tnk::StepArgs make_args(const tn::StepDesc& S) {
 }
 
 template <int NK, int NN>
-void launch_stream_nn(const tnk::StepArgs& a, hipStream_t st) {
-  uint64_t rows = 1ull << (a.nb + a.nm);
-  hipLaunchKernelGGL((tnk::k_stream<NK, NN>), dim3(grid_for(rows)), dim3(tnk::kBlock), 0, st, a);
+void launch_stream_nn(const tnk::StreamArgs& a, uint64_t rows, hipStream_t st) {
+  hipLaunchKernelGGL((tnk::k_stream<NK, NN>), dim3(grid_for(rows, 1u << 16)), dim3(tnk::kBlock),
+                     0, st, a);
 }
 
 template <int NK>
-void launch_stream_k(const tnk::StepArgs& a, hipStream_t st) {
-  switch (a.nn) {
-    case 0: launch_stream_nn<NK, 0>(a, st); break;
-    case 1: launch_stream_nn<NK, 1>(a, st); break;
-    case 2: launch_stream_nn<NK, 2>(a, st); break;
-    case 3: launch_stream_nn<NK, 3>(a, st); break;
-    default: launch_stream_nn<NK, 4>(a, st); break;
+void launch_stream_k(const tnk::StreamArgs& a, int nn, uint64_t rows, hipStream_t st) {
+  switch (nn) {
+    case 0: launch_stream_nn<NK, 0>(a, rows, st); break;
+    case 1: launch_stream_nn<NK, 1>(a, rows, st); break;
+    case 2: launch_stream_nn<NK, 2>(a, rows, st); break;
+    case 3: launch_stream_nn<NK, 3>(a, rows, st); break;
+    default: launch_stream_nn<NK, 4>(a, rows, st); break;
+  }
+}
+
+// Stream launch: row bits are the row (m) bits followed by the batch bits.
+void launch_stream(const tnk::StepArgs& s, hipStream_t st) {
+  tnk::StreamArgs a;
+  memset(&a, 0, sizeof a);
+  a.A = s.A;
+  a.B = s.B;
+  a.C = s.C;
+  a.nrow = s.nm + s.nb;
+  a.nbB = s.nb;
+  a.conjA = s.conjA;
+  a.conjB = s.conjB;
+  a.accumulate = s.accumulate;
+  for (int j = 0; j < s.nm; ++j) {
+    a.rowA[j] = s.sA_m[j];
+    a.rowC[j] = s.sC_m[j];
+  }
+  for (int j = 0; j < s.nb; ++j) {
+    a.rowA[s.nm + j] = s.sA_b[j];
+    a.rowC[s.nm + j] = s.sC_b[j];
+    a.bB[j] = s.sB_b[j];
+  }
+  for (int j = 0; j < s.nk; ++j) {
+    a.kA[j] = s.sA_k[j];
+    a.kB[j] = s.sB_k[j];
+  }
+  for (int j = 0; j < s.nn; ++j) {
+    a.nB[j] = s.sB_n[j];
+    a.nC[j] = s.sC_n[j];
+  }
+  const uint64_t rows = 1ull << a.nrow;
+  switch (s.nk) {
+    case 0: launch_stream_k<0>(a, s.nn, rows, st); break;
+    case 1: launch_stream_k<1>(a, s.nn, rows, st); break;
+    case 2: launch_stream_k<2>(a, s.nn, rows, st); break;
+    case 3: launch_stream_k<3>(a, s.nn, rows, st); break;
+    default: launch_stream_k<4>(a, s.nn, rows, st); break;
+  }
+}
+
+// Enumeration mask of a tile: merge the class-1 bits (rows of A / columns of
+// B) and the k bits, each in class order, by ascending stride; bits beyond a
+// class's size go last.  Bit j of the result is set where the merged order
+// takes a class-1 bit.
+uint32_t tile_mask(int L1, const int8_t* s1, int n1, int L2, const int8_t* s2, int n2) {
+  uint32_t mask = 0;
+  int i = 0, j = 0;
+  for (int pos = 0; pos < L1 + L2; ++pos) {
+    int k1 = i < L1 ? (i < n1 ? s1[i] : 1000 + i) : 1 << 30;
+    int k2 = j < L2 ? (j < n2 ? s2[j] : 1000 + j) : 1 << 30;
+    if (k1 <= k2) {
+      mask |= 1u << pos;
+      ++i;
+    } else {
+      ++j;
+    }
+  }
+  return mask;
+}
+
+// Largest in-tile offset of a tile whose class-1 / k bits are the lowest L1 /
+// L2 bits of their classes.
+int64_t max_tile_offset(int L1, const int8_t* s1, int n1, int L2, const int8_t* s2, int n2) {
+  int64_t m = 0;
+  for (int j = 0; j < L1 && j < n1; ++j) m += (int64_t)1 << s1[j];
+  for (int j = 0; j < L2 && j < n2; ++j) m += (int64_t)1 << s2[j];
+  return m;
+}
+
+template <int WVM, int WVN, int WM, int WN, int LK>
+tn_status launch_gemm_cfg(const tnk::StepArgs& a, int32_t precision, hipStream_t st) {
+  constexpr int MT = WVM * WM * 32, NT = WVN * WN * 16;
+  constexpr int LM = tnk::ilog2<MT>::value, LN = tnk::ilog2<NT>::value;
+  // split-BF16 tiles always walk k by 16
+  const int lk = precision == tn::PREC_SPLIT_BF16 ? 4 : LK;
+  tnk::GemmArgs g;
+  memset(&g, 0, sizeof g);
+  g.s = a;
+  g.a_mask = tile_mask(LM, a.sA_m, a.nm, lk, a.sA_k, a.nk);
+  g.b_mask = tile_mask(LN, a.sB_n, a.nn, lk, a.sB_k, a.nk);
+  int lmt = a.nm > LM ? a.nm - LM : 0, lnt = a.nn > LN ? a.nn - LN : 0;
+  uint64_t ntiles = 1ull << (a.nb + lmt + lnt);
+  if (ntiles > 0xFFFFFFFFull) return fail(TN_E_UNSUPPORTED, "too many GEMM tiles");
+  g.xcd_remap = ntiles >= 64 ? 1 : 0;
+  const bool small = max_tile_offset(LM, a.sA_m, a.nm, lk, a.sA_k, a.nk) < (1ll << 31) &&
+                     max_tile_offset(LN, a.sB_n, a.nn, lk, a.sB_k, a.nk) < (1ll << 31);
+  dim3 grid((unsigned)ntiles), blk(256);
+  if (precision == tn::PREC_SPLIT_BF16) {
+    if (small)
+      hipLaunchKernelGGL((tnk::k_gemm_sb16<WVM, WVN, WM, WN, int32_t>), grid, blk, 0, st, g);
+    else
+      hipLaunchKernelGGL((tnk::k_gemm_sb16<WVM, WVN, WM, WN, int64_t>), grid, blk, 0, st, g);
+  } else {
+    if (small)
+      hipLaunchKernelGGL((tnk::k_gemm_c64<WVM, WVN, WM, WN, LK, int32_t>), grid, blk, 0, st, g);
+    else
+      hipLaunchKernelGGL((tnk::k_gemm_c64<WVM, WVN, WM, WN, LK, int64_t>), grid, blk, 0, st, g);
+  }
+  return TN_OK;
+}
+
+tn_status launch_gemm(const tnk::StepArgs& a, int32_t precision, int32_t tile, hipStream_t st) {
+  switch (tile) {
+    case 0: return launch_gemm_cfg<2, 2, 2, 2, 4>(a, precision, st);   // 128 x 64
+    case 1: return launch_gemm_cfg<4, 1, 1, 2, 4>(a, precision, st);   // 128 x 32
+    case 2: return launch_gemm_cfg<4, 1, 2, 1, 4>(a, precision, st);   // 256 x 16
+    case 3: return launch_gemm_cfg<2, 2, 2, 4, 4>(a, precision, st);   // 128 x 128
+    case 4: return launch_gemm_cfg<2, 2, 4, 2, 4>(a, precision, st);   // 256 x 64
+    case 5: return launch_gemm_cfg<2, 2, 2, 2, 5>(a, precision, st);   // 128 x 64, k tile 32
+    default: return fail(TN_E_INVALID, "unknown GEMM tile configuration");
   }
 }
 
 // Launch one contraction (forward or adjoint) with the given kernel family.
-tn_status launch_step(int32_t kind, int32_t chunks, const tnk::StepArgs& a0, float2* scratch,
-                      hipStream_t st) {
+tn_status launch_step(int32_t kind, int32_t chunks, int32_t tile, const tnk::StepArgs& a0,
+                      float2* scratch, int32_t precision, hipStream_t st) {
   tnk::StepArgs a = a0;
   const uint64_t n_out = 1ull << (a.nb + a.nm + a.nn);
   if (kind == tn::KIND_SPLITK) {
@@ -101,13 +215,10 @@ tn_status launch_step(int32_t kind, int32_t chunks, const tnk::StepArgs& a0, flo
     hipLaunchKernelGGL(tnk::k_splitk_reduce, dim3(grid_for(n_out, 1u << 30)), dim3(tnk::kBlock),
                        0, st, a, nch);
   } else if (kind == tn::KIND_STREAM && a.nk <= 4 && a.nn <= 4) {
-    switch (a.nk) {
-      case 0: launch_stream_k<0>(a, st); break;
-      case 1: launch_stream_k<1>(a, st); break;
-      case 2: launch_stream_k<2>(a, st); break;
-      case 3: launch_stream_k<3>(a, st); break;
-      default: launch_stream_k<4>(a, st); break;
-    }
+    launch_stream(a, st);
+  } else if (kind == tn::KIND_GEMM) {
+    tn_status s = launch_gemm(a, precision, tile, st);
+    if (s != TN_OK) return s;
   } else {
     hipLaunchKernelGGL(tnk::k_simple, dim3(grid_for(n_out)), dim3(tnk::kBlock), 0, st, a);
   }
@@ -116,20 +227,10 @@ tn_status launch_step(int32_t kind, int32_t chunks, const tnk::StepArgs& a0, flo
   return TN_OK;
 }
 
-// Kernel family and split-k chunks for an arbitrary (adjoint) shape, using
-// the plan's rule.
+// Kernel family and split-k chunks for an arbitrary (adjoint) shape.
 int32_t kind_for(const tnk::StepArgs& a, uint32_t flags, int32_t* chunks) {
-  int out_bits = a.nb + a.nm + a.nn;
-  *chunks = 0;
-  if (a.nk >= 8 && out_bits <= 12) {
-    int cl = a.nk - 10 > 8 ? a.nk - 10 : 8;
-    if (cl > a.nk) cl = a.nk;
-    *chunks = 1 << (a.nk - cl);
-    return tn::KIND_SPLITK;
-  }
-  if (flags & TN_FLAG_SIMPLE_KERNELS) return tn::KIND_SIMPLE;
-  if (a.nk <= 4 && a.nn <= 4 && a.nb <= 12) return tn::KIND_STREAM;
-  return tn::KIND_SIMPLE;
+  int64_t scratch;
+  return tn::choose_kind(a.nb, a.nm, a.nn, a.nk, flags, chunks, &scratch);
 }
 
 struct Ctx {
@@ -170,7 +271,7 @@ tn_status run_step(const Ctx& c, int k, uint64_t outer_val, Probe* probe = nullp
   a.C = reinterpret_cast<float2*>(c.ws + S.c_off);
   bool timed = probe && !probe->done && probe->step == k;
   if (timed) TN_HIP_CHECK(hipEventRecord(probe->start, c.st));
-  tn_status s = launch_step(S.kind, S.splitk_chunks, a, c.scratch, c.st);
+  tn_status s = launch_step(S.kind, S.splitk_chunks, S.tile, a, c.scratch, p.precision, c.st);
   if (timed && s == TN_OK) {
     TN_HIP_CHECK(hipEventRecord(probe->stop, c.st));
     probe->done = true;
@@ -199,6 +300,7 @@ tn_status tn_plan_create(int32_t n_tensors, const int32_t* ranks, const int32_t*
   tn_plan_options o;
   memset(&o, 0, sizeof o);
   o.max_resident_bits = -1;
+  o.gemm_config = -1;
   if (opts) o = *opts;
   try {
     tn_plan_s* h = new tn_plan_s();
@@ -206,7 +308,7 @@ tn_status tn_plan_create(int32_t n_tensors, const int32_t* ranks, const int32_t*
     std::string err = tn::build_plan(h->p, n_tensors, ranks, index_ids, n_index, index_dims,
                                      n_open, open_ids, n_steps, path, n_sliced, sliced_ids,
                                      o.precision, o.max_resident_bits, o.workspace_limit,
-                                     o.flags, &unsup);
+                                     o.flags, o.gemm_config, o.tune, o.n_tune, &unsup);
     if (!err.empty()) {
       delete h;
       return fail(unsup ? TN_E_UNSUPPORTED : TN_E_INVALID, err);
@@ -271,6 +373,7 @@ tn_status tn_plan_step(tn_plan_t plan, int32_t step, tn_step_info* out) {
   out->nn = (int32_t)S.nB.size();
   out->nk = (int32_t)S.kA.size();
   out->inst_bits = S.inst_bits;
+  out->tile = S.tile;
   out->cmac = S.cmac;
   copy_bits(out->sA_b, S.bA);
   copy_bits(out->sB_b, S.bB);
@@ -405,14 +508,101 @@ extern "C" {
 tn_status tn_contract_backward(tn_plan_t plan, const void* const* leaves, const void* grad_out,
                                void* const* grad_leaves, void* ws, size_t ws_bytes,
                                void* stream) {
-  (void)plan;
-  (void)leaves;
-  (void)grad_out;
-  (void)grad_leaves;
-  (void)ws;
-  (void)ws_bytes;
-  (void)stream;
-  return fail(TN_E_UNSUPPORTED, "backward not built yet");
+  if (!plan || !leaves || !grad_out || !grad_leaves) return fail(TN_E_INVALID, "NULL argument");
+  const tn::Plan& p = plan->p;
+  if (p.outer_bits > 0)
+    return fail(TN_E_UNSUPPORTED, "backward needs every slice resident (no outer iterations)");
+  if ((int64_t)ws_bytes < p.workspace_bwd_bytes || !ws)
+    return fail(TN_E_WORKSPACE, "workspace smaller than tn_plan_info.workspace_backward_bytes");
+  for (int t = 0; t < p.n_tensors; ++t)
+    if (!leaves[t]) return fail(TN_E_INVALID, "NULL leaf pointer");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* W = static_cast<char*>(ws);
+  float2* scratch = reinterpret_cast<float2*>(W + ((p.bwd_arena_bytes + 255) / 256) * 256);
+  const int n = p.n_tensors;
+  auto fwd_ptr = [&](int node) -> float2* {
+    if (node < n) return const_cast<float2*>(static_cast<const float2*>(leaves[node]));
+    return reinterpret_cast<float2*>(W + p.bwd_fwd_off[node]);
+  };
+  // forward, keeping every intermediate
+  for (int k : p.sched) {
+    const tn::StepDesc& S = p.steps[k];
+    tnk::StepArgs a = make_args(S);
+    a.A = fwd_ptr(S.a);
+    a.B = fwd_ptr(S.b);
+    a.C = fwd_ptr(S.c);
+    tn_status s = launch_step(S.kind, S.splitk_chunks, S.tile, a, scratch, p.precision, st);
+    if (s != TN_OK) return s;
+  }
+  // gradient of the root: the output gradient, broadcast over resident slices
+  const int root = n + (n - 1) - 1;
+  tnk::RootGradArgs rg;
+  memset(&rg, 0, sizeof rg);
+  rg.grad_out = static_cast<const double2*>(grad_out);
+  rg.open_bits = p.open_bits;
+  rg.res_bits = p.resident_bits;
+  copy_bits(rg.s_open, p.root_open_log2);
+  copy_bits(rg.s_res, p.root_res_log2);
+  if (n == 1) {
+    if (!grad_leaves[0]) return TN_OK;
+    rg.dst = static_cast<float2*>(grad_leaves[0]);
+    rg.accumulate = 1;
+  } else {
+    rg.dst = reinterpret_cast<float2*>(W + p.bwd_grad_off[root]);
+  }
+  hipLaunchKernelGGL(tnk::k_root_grad, dim3(grid_for(1ull << (p.open_bits + p.resident_bits))),
+                     dim3(tnk::kBlock), 0, st, rg);
+  TN_HIP_CHECK(hipGetLastError());
+  // reverse sweep: dA = dC . B^H, dB = A^H . dC
+  for (int i = (int)p.sched.size() - 1; i >= 0; --i) {
+    const tn::StepDesc& S = p.steps[p.sched[i]];
+    float2* gC = reinterpret_cast<float2*>(W + p.bwd_grad_off[S.c]);
+    const int nb = (int)S.bA.size(), nm = (int)S.mA.size(), nn = (int)S.nB.size(),
+              nk = (int)S.kA.size();
+    float2* dA = S.a < n ? static_cast<float2*>(grad_leaves[S.a])
+                         : reinterpret_cast<float2*>(W + p.bwd_grad_off[S.a]);
+    float2* dB = S.b < n ? static_cast<float2*>(grad_leaves[S.b])
+                         : reinterpret_cast<float2*>(W + p.bwd_grad_off[S.b]);
+    if (dA) {
+      tnk::StepArgs a;
+      memset(&a, 0, sizeof a);
+      a.nb = nb; a.nm = nm; a.nn = nk; a.nk = nn;
+      copy_bits(a.sA_b, S.bC); copy_bits(a.sA_m, S.mC); copy_bits(a.sA_k, S.nC);
+      copy_bits(a.sB_b, S.bB); copy_bits(a.sB_k, S.nB); copy_bits(a.sB_n, S.kB);
+      copy_bits(a.sC_b, S.bA); copy_bits(a.sC_m, S.mA); copy_bits(a.sC_n, S.kA);
+      a.A = gC;
+      a.B = fwd_ptr(S.b);
+      a.C = dA;
+      a.conjB = 1;
+      a.accumulate = S.a < n ? 1 : 0;
+      int32_t ch;
+      int64_t scr;
+      int32_t kind = tn::choose_kind(a.nb, a.nm, a.nn, a.nk, p.flags, &ch, &scr);
+      int32_t tile = kind == tn::KIND_GEMM ? tn::choose_tile(p, a.nm, a.nn, a.nk) : -1;
+      tn_status s = launch_step(kind, ch, tile, a, scratch, p.precision, st);
+      if (s != TN_OK) return s;
+    }
+    if (dB) {
+      tnk::StepArgs a;
+      memset(&a, 0, sizeof a);
+      a.nb = nb; a.nm = nk; a.nn = nn; a.nk = nm;
+      copy_bits(a.sA_b, S.bA); copy_bits(a.sA_m, S.kA); copy_bits(a.sA_k, S.mA);
+      copy_bits(a.sB_b, S.bC); copy_bits(a.sB_k, S.mC); copy_bits(a.sB_n, S.nC);
+      copy_bits(a.sC_b, S.bB); copy_bits(a.sC_m, S.kB); copy_bits(a.sC_n, S.nB);
+      a.A = fwd_ptr(S.a);
+      a.B = gC;
+      a.C = dB;
+      a.conjA = 1;
+      a.accumulate = S.b < n ? 1 : 0;
+      int32_t ch;
+      int64_t scr;
+      int32_t kind = tn::choose_kind(a.nb, a.nm, a.nn, a.nk, p.flags, &ch, &scr);
+      int32_t tile = kind == tn::KIND_GEMM ? tn::choose_tile(p, a.nm, a.nn, a.nk) : -1;
+      tn_status s = launch_step(kind, ch, tile, a, scratch, p.precision, st);
+      if (s != TN_OK) return s;
+    }
+  }
+  return TN_OK;
 }
 
 tn_status tn_permute(const void* in, void* out, int32_t nbits, const int8_t* in_log2,

@@ -1,0 +1,119 @@
+"""Kernel-family parity on single pairwise contractions (GPU).
+
+Each case is a two-tensor network whose free and batch indices are open, so
+the whole product tensor comes back through the C ABI.  Axis orders are
+shuffled so the operands' bit strides are scattered, and shapes are chosen
+to land on every kernel family (GEMM tile configurations including partial
+tiles, split-k, stream, plain).  Reference: the oracle's pairwise step in
+complex128.  Tolerances: complex64 1e-5, split-BF16 1e-3 relative (Frobenius)
+-- the stated bounds for the two precisions.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import tn_oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _case(rng, nb, nm, nn, nk, d4=0):
+    """Index ids: batch, row, column, summed; d4 of the row indices get dim 4."""
+    ids = iter(range(1000))
+    bat = [next(ids) for _ in range(nb)]
+    row = [next(ids) for _ in range(nm)]
+    col = [next(ids) for _ in range(nn)]
+    summ = [next(ids) for _ in range(nk)]
+    dims = {i: 2 for i in bat + row + col + summ}
+    for i in row[:d4]:
+        dims[i] = 4
+    la = list(rng.permutation(bat + row + summ))
+    lb = list(rng.permutation(bat + summ + col))
+    la = [int(x) for x in la]
+    lb = [int(x) for x in lb]
+    a = (rng.standard_normal([dims[i] for i in la]) + 1j * rng.standard_normal([dims[i] for i in la]))
+    b = (rng.standard_normal([dims[i] for i in lb]) + 1j * rng.standard_normal([dims[i] for i in lb]))
+    open_ids = list(rng.permutation(bat + row + col))
+    open_ids = [int(x) for x in open_ids]
+    return [a, b], [la, lb], dims, open_ids
+
+
+CASES = [
+    # (nb, nm, nn, nk, d4, expected kind)
+    (0, 10, 7, 8, 0, "gemm"),      # 128x64 tiles
+    (1, 9, 6, 5, 0, "gemm"),
+    (0, 10, 5, 6, 0, "gemm"),      # 128x32 tiles
+    (2, 8, 4, 7, 0, "gemm"),       # 256x16 tiles
+    (0, 5, 3, 5, 0, "gemm"),       # partial row and column tiles
+    (0, 5, 6, 3, 0, "gemm"),       # partial row and k tiles (operands swap roles)
+    (0, 6, 9, 9, 1, "gemm"),       # dim-4 rows
+    (0, 12, 3, 2, 0, "stream"),
+    (2, 10, 2, 4, 1, "stream"),
+    (3, 4, 2, 3, 0, "stream"),     # batch bits inside a workgroup's rows: B through the cache
+    (0, 7, 4, 4, 0, "stream"),     # fewer rows than a workgroup
+    (0, 2, 2, 14, 0, "splitk"),
+    (3, 1, 0, 10, 0, "splitk"),
+    (0, 3, 3, 6, 0, "simple"),
+]
+
+
+@pytest.mark.parametrize("precision", ["c64", "split_bf16"])
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "b%dm%dn%dk%d_%s" % (c[0], c[1], c[2], c[3], c[5]))
+def test_pairwise_kernels(case, precision):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2107_09793_amd import Plan
+    nb, nm, nn, nk, d4, kind = case
+    rng = np.random.default_rng([nb, nm, nn, nk, d4])
+    tensors, labels, dims, open_ids = _case(rng, nb, nm, nn, nk, d4)
+    pl = Plan(labels, dims, open_ids, [(0, 1)], precision=precision)
+    st = pl.step(0)
+    assert st["kind_name"] == kind, st["kind_name"]
+    dev = torch.device("cuda:0")
+    leaves = [torch.from_numpy(t.astype(np.complex64)).to(dev) for t in tensors]
+    got = pl.contract(leaves).cpu().numpy()
+    ref = tn_oracle.contract([t.astype(np.complex64).astype(np.complex128) for t in tensors],
+                             labels, dims, open_ids, [(0, 1)])
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    tol = 1e-5 if (precision == "c64" or kind != "gemm") else 1e-3
+    assert err <= tol, err
+    if precision == "split_bf16" and kind == "gemm":
+        assert err > 1e-9   # really ran in reduced precision
+        assert err <= 1e-4  # three-product split: ~2^-16 relative
+
+
+def test_gemm_deterministic_run_to_run():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2107_09793_amd import Plan
+    rng = np.random.default_rng(3)
+    tensors, labels, dims, open_ids = _case(rng, 1, 10, 7, 8)
+    pl = Plan(labels, dims, open_ids, [(0, 1)])
+    dev = torch.device("cuda:0")
+    leaves = [torch.from_numpy(t.astype(np.complex64)).to(dev) for t in tensors]
+    x = pl.contract(leaves).cpu().numpy()
+    y = pl.contract(leaves).cpu().numpy()
+    assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("precision", ["c64", "split_bf16"])
+@pytest.mark.parametrize("cfg", range(6))
+def test_every_gemm_tile_config(cfg, precision):
+    """Each compiled tile configuration, forced on a full and a partial tile shape."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2107_09793_amd import Plan
+    dev = torch.device("cuda:0")
+    for shape in ((1, 10, 8, 7, 0), (0, 6, 5, 5, 1)):
+        rng = np.random.default_rng([cfg, *shape])
+        tensors, labels, dims, open_ids = _case(rng, *shape)
+        pl = Plan(labels, dims, open_ids, [(0, 1)], precision=precision, gemm_config=cfg)
+        st = pl.step(0)
+        assert st["kind_name"] == "gemm" and st["tile"] == cfg
+        leaves = [torch.from_numpy(t.astype(np.complex64)).to(dev) for t in tensors]
+        got = pl.contract(leaves).cpu().numpy()
+        ref = tn_oracle.contract([t.astype(np.complex64).astype(np.complex128) for t in tensors],
+                                 labels, dims, open_ids, [(0, 1)])
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        assert err <= (1e-5 if precision == "c64" else 1e-4), (shape, err)
