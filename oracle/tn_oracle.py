@@ -47,9 +47,11 @@ def pairwise(a, la, b, lb, open_ids):
     return c.reshape(shape), batch + fa + fb
 
 
-def contract_slice(tensors, labels, open_ids, path, sliced, values):
+def contract_slice(tensors, labels, open_ids, path, sliced, values, on_step=None):
     """One slice: leaves with sliced indices fixed, contracted along ``path``.
-    Returns the result with axes in ``open_ids`` order."""
+    Returns the result with axes in ``open_ids`` order.  ``on_step(k)``, if
+    given, is called after step k; returning False stops the contraction early
+    (the function then returns None), which lets a caller time a prefix."""
     fixed = dict(zip(sliced, values))
     pool = {}
     n = len(tensors)
@@ -65,6 +67,8 @@ def contract_slice(tensors, labels, open_ids, path, sliced, values):
         a, la = pool.pop(i)
         b, lb = pool.pop(j)
         pool[n + k] = pairwise(a, la, b, lb, open_ids)
+        if on_step is not None and on_step(k) is False:
+            return None
     if len(pool) != 1:
         raise ValueError("path does not contract the network to one tensor")
     (x, lab), = pool.values()

@@ -1,0 +1,60 @@
+"""Writes precision_slices_seed0.json: complex128 oracle values of sampled
+slices of the 53-qubit depth-12 workload (seed 0).
+
+Calls only the oracle (tn_oracle.contract) on inputs from the seeded
+generators.  Each requested slice is contracted as the sum of its 4
+sub-slices over two further sliced indices (picked by the same greedy
+slicer), which bounds host memory; the sum of sub-slices is exactly the slice
+(Eq. sliced_sum).
+
+    python tests/golden/make_precision_slices.py [slice ids ...]
+"""
+
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import tn_oracle  # noqa: E402
+from tngen import slicing, workloads  # noqa: E402
+
+
+def fingerprint(w):
+    h = hashlib.sha256()
+    h.update(json.dumps([list(map(int, p)) for p in w.path]).encode())
+    h.update(json.dumps(list(map(int, w.sliced))).encode())
+    return h.hexdigest()[:16]
+
+
+def main():
+    ids = [int(x) for x in sys.argv[1:]] or [0, 1, 513, 1023]
+    w = workloads.build("precision", seed=0)
+    ts = slicing.TreeSets(w.tn.labels, w.tn.dims, w.tn.open, w.path)
+    ext = slicing.greedy_slices(ts, n_slice=len(w.sliced) + 2)
+    assert ext[:len(w.sliced)] == list(w.sliced)
+    extra = ext[len(w.sliced):]
+    n_sub = int(np.prod([w.tn.dims[e] for e in extra]))
+    out = []
+    for sid in ids:
+        t0 = time.time()
+        sub = [sid * n_sub + j for j in range(n_sub)]
+        v = tn_oracle.contract(w.tn.tensors, w.tn.labels, w.tn.dims, w.tn.open, w.path,
+                               list(w.sliced) + list(extra), slice_ids=sub)
+        v = complex(v)
+        out.append([sid, v.real, v.imag])
+        print(f"slice {sid}: {v!r} ({time.time() - t0:.0f} s)", flush=True)
+    doc = dict(source="oracle/tn_oracle.contract, complex128, sub-sliced over 2 extra indices",
+               workload="precision", seed=0, fingerprint=fingerprint(w),
+               extra_sliced=list(map(int, extra)), slices=out)
+    with open(os.path.join(HERE, "precision_slices_seed0.json"), "w") as f:
+        json.dump(doc, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -108,25 +108,27 @@ def greedy_slices(ts, n_slice=None, cap_log2=None, max_slices=64):
     return out
 
 
-def search(labels, dims, kept, n_slice=None, cap_log2=None, trials=8, seed=0,
-           temperature=0.3):
+def search(labels, dims, kept, n_slice=None, cap_log2=None, trials=8, seed=0):
     """Best of a deterministic greedy path plus ``trials`` seeded randomised
-    ones, each sliced greedily; ranked by (meets cap, largest per-slice
-    intermediate, multiply-adds with reuse)."""
+    ones (temperature drawn from a fixed list, cost weight alpha ~ U(0.5, 2)),
+    each sliced greedily; ranked by (meets the cap, multiply-adds with reuse,
+    largest per-slice intermediate)."""
     best = None
+    temps = (0.0, 0.05, 0.1, 0.2, 0.3, 0.5, 1.0)
     for t in range(trials + 1):
         if t == 0:
             path = greedy_path(labels, dims, kept)
         else:
             rng = np.random.default_rng([seed, 2, t])
-            alpha = float(rng.uniform(0.75, 1.5))
-            path = greedy_path(labels, dims, kept, seed=seed * 1000 + t,
-                               temperature=temperature, alpha=alpha)
+            temp = float(rng.choice(temps))
+            alpha = float(rng.uniform(0.5, 2.0))
+            path = greedy_path(labels, dims, kept, seed=seed * 100000 + t,
+                               temperature=temp, alpha=alpha)
         ts = TreeSets(labels, dims, kept, path)
-        sl = greedy_slices(ts, n_slice=n_slice, cap_log2=cap_log2)
+        sl = greedy_slices(ts, n_slice=n_slice)
         st = ts.stats(sl)
         ok = cap_log2 is None or st["max_log2"] <= cap_log2 + 1e-9
-        key = (not ok, st["max_log2"], st["flop_reuse"])
+        key = (not ok, st["flop_reuse"], st["max_log2"])
         if best is None or key < best[0]:
             best = (key, path, sl, st)
     return best[1], best[2], best[3]

@@ -40,13 +40,13 @@ class Workload:
 
 
 CONFIGS = {
-    "plain": dict(kind="grid", rows=3, cols=4, depth=8, n_slice=0),
-    "sliced": dict(kind="grid", rows=5, cols=6, depth=14, n_slice=6, cap_log2=26),
+    "plain": dict(kind="grid", rows=3, cols=4, depth=8, n_slice=0, trials=8),
+    "sliced": dict(kind="grid", rows=5, cols=6, depth=14, n_slice=6, cap_log2=26, trials=64),
     "precision": dict(kind="grid", rows=6, cols=9, depth=12, inactive=((0, 4),),
-                      n_slice=10, cap_log2=30),
-    "bosonic": dict(kind="gbs", rows=4, cols=4, depth=6, d=4, n_slice=2),
+                      n_slice=10, cap_log2=30, trials=96),
+    "bosonic": dict(kind="gbs", rows=4, cols=4, depth=6, d=4, n_slice=2, trials=96),
     "gradient": dict(kind="grid", rows=4, cols=5, depth=10, batch=256, trainable=True,
-                     n_slice=0),
+                     n_slice=0, trials=8),
 }
 
 
