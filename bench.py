@@ -1,15 +1,18 @@
 """Benchmark: sliced contraction of one amplitude on one MI355X.
 
-Workload (default): 30-qubit 5x6 grid random circuit, depth 14, one
-amplitude, 6 sliced indices = 64 slices, all slices in one tn_contract call
-with slice-independent work done once.  A step is one full tn_contract (all
-64 slices, every contraction step, the float64 slice sum) with leaves already
-resident in HBM.
+Workload (default): 53-qubit random circuit on a 6x9 grid (site (0,4)
+inactive), depth 12, one amplitude, 10 sliced indices = 1024 slices, per-slice
+intermediates <= 2^30 entries; all slices in one tn_contract call with the
+slice-independent work done once.  A step is one full tn_contract (all 1024
+slices, every contraction step, the float64 slice sum) with leaves already
+resident in HBM.  Both precisions run by default: complex64 (the reported
+value) and split-BF16, each with its relative error against complex128 oracle
+values of sampled slices (stored under tests/golden/).
 
 Prints one JSON line: complex GFLOP/s (2 x multiply-adds executed / time),
 slices/s, the roofline of the dominant step (timed with HIP events on the
 launch stream during the timed region) and the CPU oracle timed on a bounded
-sample of slices.
+sample of the same workload.
 """
 
 import argparse
@@ -28,6 +31,7 @@ PEAKS = {  # MI355X published peaks
     "mfma_c64": 157.3,             # TFLOP/s, FP32 matrix
     "mfma_split_bf16": 2516.6,     # TFLOP/s, BF16 dense matrix
     "alu": 78.6,                   # TFLOP/s, FP32 vector FMA without packed math
+                                   # (256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz)
 }
 
 WORKLOAD_DESC = {
@@ -41,71 +45,123 @@ WORKLOAD_DESC = {
 }
 
 
-def dominant_step(plan, leaves, info, steps, torch):
-    """Step with the longest single execution among the heaviest candidates."""
-    cand = sorted(range(len(steps)), key=lambda k: -steps[k]["cmac"])[:3]
-    cand += sorted(range(len(steps)), key=lambda k: -steps[k]["bytes"])[:2]
+def launch_units(plan, steps):
+    """What one launch computes: a fused chain (all its steps) or one step.
+    Returns {first step of the unit: dict(kind, cmac, bytes, phase, steps)} with
+    the algorithmic HBM bytes (each operand read once, the result written
+    once; a chain's intermediates stay on chip)."""
+    units = {}
+    chains = plan.chains() if plan.info()["n_chains"] else []
+    for k, s in enumerate(steps):
+        if s["chain"] >= 0:
+            continue
+        units[k] = dict(kind=s["kind_name"], cmac=s["cmac"], bytes=s["bytes"], phase=s["phase"],
+                        steps=[k], shape=dict(nb=s["nb"], nm=s["nm"], nn=s["nn"], nk=s["nk"]))
+    for ch in chains:
+        mem = [steps[d["step"]] for d in ch["st"]]
+        f, l = mem[0], mem[-1]
+        el = 2 ** (f["nb"] + f["nm"] + f["nk"]) + 2 ** (l["nb"] + l["nm"] + l["nn"])
+        el += sum(2 ** (m["nb"] + m["nk"] + m["nn"]) for m in mem)
+        units[ch["first"]] = dict(kind="chain", cmac=sum(m["cmac"] for m in mem), bytes=8.0 * el,
+                                  phase=ch["phase"], steps=[d["step"] for d in ch["st"]],
+                                  shape=[dict(nb=m["nb"], nm=m["nm"], nn=m["nn"], nk=m["nk"])
+                                         for m in mem])
+    return units
+
+
+def dominant_unit(plan, leaves, info, units, torch):
+    """Launch with the largest total time (first execution's duration times
+    its executions per contraction) among the heaviest candidates; returns
+    (first step of the unit, executions)."""
+    n_outer = 1 << info["n_outer_bits"]
+    execs = {k: (n_outer if u["phase"] == 1 else 1) for k, u in units.items()}
+    keys = list(units)
+    cand = sorted(keys, key=lambda k: -units[k]["cmac"] * execs[k])[:4]
+    cand += sorted(keys, key=lambda k: -units[k]["bytes"] * execs[k])[:4]
     best, best_ms = None, -1.0
     for k in dict.fromkeys(cand):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         plan.contract(leaves, probe=(k, e0, e1))
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
+        ms = e0.elapsed_time(e1) * execs[k]
         if ms > best_ms:
             best, best_ms = k, ms
-    return best
+    return best, execs[best]
 
 
-def roofline(step, avg_s, precision):
-    kind = step["kind_name"]
+def roofline(unit, avg_s, precision):
+    """The unit's bound is the larger of its HBM time (algorithmic bytes at
+    8 TB/s) and its compute time (MFMA for GEMM steps at the precision's
+    peak, counting the three products of split-BF16; FP32 vector FMA for the
+    others); achieved is measured in that bound's unit."""
+    kind = unit["kind"]
     if kind == "gemm":
-        peak = PEAKS["mfma_" + precision]
-        ach = 8.0 * step["cmac"] / avg_s / 1e12
-        return dict(bound="mfma", achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak)
-    if kind in ("stream", "splitk"):
-        ach = step["bytes"] / avg_s / 1e9
+        flops = 8.0 * unit["cmac"] * (3.0 if precision == "split_bf16" else 1.0)
+        peak, cbound = PEAKS["mfma_" + precision], "mfma"
+    else:
+        flops = 8.0 * unit["cmac"]
+        peak, cbound = PEAKS["alu"], "alu"
+    t_mem = unit["bytes"] / (PEAKS["hbm"] * 1e9)
+    t_cmp = flops / (peak * 1e12)
+    if t_mem >= t_cmp:
+        ach = unit["bytes"] / avg_s / 1e9
         return dict(bound="hbm", achieved=ach, peak=PEAKS["hbm"], unit="GB/s",
                     frac=ach / PEAKS["hbm"])
-    ach = 8.0 * step["cmac"] / avg_s / 1e12
-    return dict(bound="alu", achieved=ach, peak=PEAKS["alu"], unit="TFLOP/s",
-                frac=ach / PEAKS["alu"])
+    ach = flops / avg_s / 1e12
+    return dict(bound=cbound, achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak)
 
 
-def measured_traffic(step, precision):
-    """HBM bytes of the dominant step from the committed counter summary
-    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the summary is
-    for another step shape or precision, or the GEMM source changed since."""
+KERNEL_SOURCES = {
+    "gemm": ("paper_2107_09793_amd/csrc/kernels_gemm.h", "paper_2107_09793_amd/csrc/kernels_common.h"),
+    "stream": ("paper_2107_09793_amd/csrc/kernels_basic.h", "paper_2107_09793_amd/csrc/kernels_common.h"),
+    "chain": ("paper_2107_09793_amd/csrc/kernels_chain.h", "paper_2107_09793_amd/csrc/kernels_common.h"),
+}
+
+
+def kernel_sha(kind):
     import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES.get(kind, KERNEL_SOURCES["stream"]):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, unit, precision):
+    """HBM bytes per launch of the dominant launch from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when there is
+    no summary for this workload and precision, it is for another launch, or
+    the kernel source changed since the counters were taken."""
     import re
-    path = os.path.join(ROOT, "profiles", f"hbm_traffic_gemm_{precision}_sliced30q.md")
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}_{precision}.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
     m_b = re.search(r"traffic_bytes:\s*([0-9.eE+]+)", txt)
     m_h = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
-    m_s = re.search(r"step_shape:\s*b(\d+) m(\d+) n(\d+) k(\d+)", txt)
+    m_s = re.search(r"launch:\s*(\w+) steps ([0-9,]+)", txt)
     if not (m_b and m_h and m_s):
         return None
-    h = hashlib.sha256()
-    for f in ("paper_2107_09793_amd/csrc/kernels_gemm.h", "paper_2107_09793_amd/csrc/kernels_common.h"):
-        h.update(open(os.path.join(ROOT, f), "rb").read())
-    shape = tuple(int(x) for x in m_s.groups())
-    if h.hexdigest()[:16] != m_h.group(1) or shape != (step["nb"], step["nm"], step["nn"], step["nk"]):
+    kind = m_s.group(1)
+    steps = [int(x) for x in m_s.group(2).split(",")]
+    if kind != unit["kind"] or kernel_sha(kind) != m_h.group(1) or steps != unit["steps"]:
         return None
     return float(m_b.group(1))
 
 
-def cpu_baseline(w, n_sample, gpu_per_slice):
-    """The oracle (numpy complex128, one slice at a time, no reuse) on a
-    bounded sample of slices; returns its throughput and the GPU's relative
-    error on the same slices."""
-    from oracle import tn_oracle
+def oracle_cores():
     try:
         from threadpoolctl import threadpool_info
-        cores = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+        return max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
     except Exception:
-        cores = len(os.sched_getaffinity(0))
+        return len(os.sched_getaffinity(0))
+
+
+def cpu_baseline_slices(w, n_sample, gpu_per_slice):
+    """The oracle (numpy complex128, one slice at a time, no reuse) on the
+    first ``n_sample`` slices; returns its throughput and the GPU's relative
+    error on the same slices."""
+    from oracle import tn_oracle
     n_sl = 1
     for e in w.sliced:
         n_sl *= w.tn.dims[e]
@@ -118,52 +174,109 @@ def cpu_baseline(w, n_sample, gpu_per_slice):
     got = gpu_per_slice.reshape(gpu_per_slice.shape[0], -1)[ids]
     rms = np.sqrt(np.mean(np.abs(ref) ** 2))
     err = float(np.max(np.abs(got - ref)) / rms)
-    return dt, len(ids), cores, err
+    return dict(seconds=dt, cmac=None, slices=len(ids), rel_err=err,
+                sample=f"{len(ids)} whole slices")
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="sliced", choices=sorted(WORKLOAD_DESC))
-    ap.add_argument("--precision", default="c64", choices=["c64", "split_bf16"])
-    ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cpu-sample", type=int, default=3, help="slices the oracle times (0 = skip)")
-    ap.add_argument("--no-reuse", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): slices are independent, "
-              "so the multi-GPU layout is one slice range per GPU plus one all-reduce of the "
-              "float64 partial sums; this build measures the single-GPU share.", file=sys.stderr)
-        sys.exit(2)
+def oracle_step_costs(w):
+    """Multiply-adds of each pairwise step of one slice as the oracle runs it
+    (product of the dims of all indices of both operands, sliced ones fixed)."""
+    sl = set(w.sliced)
+    labs = {t: set(l) - sl for t, l in enumerate(w.tn.labels)}
+    opn = set(w.tn.open)
+    n = len(w.tn.labels)
+    costs = []
+    for k, (i, j) in enumerate(w.path):
+        a, b = labs.pop(i), labs.pop(j)
+        costs.append(float(np.prod([w.tn.dims[x] for x in a | b], dtype=np.float64)))
+        labs[n + k] = (a | b) - ((a & b) - opn)
+    return costs
 
-    import torch
+
+def cpu_baseline_prefix(w, budget_s):
+    """The oracle on a prefix of slice 0's path: steps run in path order until
+    the next one would overrun ``budget_s`` (estimated from the rate so far)."""
+    from oracle import tn_oracle
+    costs = oracle_step_costs(w)
+    vals = tn_oracle.decode_slice(0, [w.tn.dims[e] for e in w.sliced])
+    st = dict(done=0, cmac=0.0, t0=time.perf_counter())
+
+    def on_step(k):
+        st["done"] = k + 1
+        st["cmac"] += costs[k]
+        el = time.perf_counter() - st["t0"]
+        if k + 1 >= len(costs):
+            return True
+        rate = st["cmac"] / max(el, 1e-9)
+        return el + costs[k + 1] / rate <= budget_s
+
+    tn_oracle.contract_slice(w.tn.tensors, w.tn.labels, w.tn.open, w.path, w.sliced, vals,
+                             on_step=on_step)
+    dt = time.perf_counter() - st["t0"]
+    return dict(seconds=dt, cmac=st["cmac"], slices=None, rel_err=None,
+                sample=f"first {st['done']} of {len(costs)} steps of slice 0 "
+                       f"({st['cmac']:.3e} of {sum(costs):.3e} multiply-adds of a slice)",
+                slice_cmac=sum(costs))
+
+
+def golden(workload, seed):
+    """complex128 oracle values of sampled slices, written by
+    tests/golden/make_precision_slices.py (oracle only), or None."""
+    path = os.path.join(ROOT, "tests", "golden", f"{workload}_slices_seed{seed}.json")
+    if not os.path.exists(path):
+        return None
+    doc = json.load(open(path))
+    return [s[0] for s in doc["slices"]], np.array([s[1] + 1j * s[2] for s in doc["slices"]])
+
+
+def permute_roofline(torch, nbits=28, reps=10, seed=0):
+    """The LDS-tiled bit permutation (tn_permute) on a 2^nbits complex64
+    tensor under a seeded random permutation of its bits: 16 bytes moved per
+    element (read + write), timed with HIP events on the current stream."""
+    from paper_2107_09793_amd import permute
+    rng = np.random.default_rng([seed, 5])
+    pin = list(range(nbits))
+    pout = [int(v) for v in rng.permutation(nbits)]
+    x = torch.randn(1 << nbits, dtype=torch.complex64, device="cuda")
+    y = torch.empty_like(x)
+    permute(x, pin, pout, out=y)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        permute(x, pin, pout, out=y)
+    e1.record()
+    torch.cuda.synchronize()
+    avg = e0.elapsed_time(e1) / reps / 1e3
+    gbs = 16.0 * (1 << nbits) / avg / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return dict(bound="hbm", achieved=gbs, peak=PEAKS["hbm"], unit="GB/s",
+                frac=gbs / PEAKS["hbm"], traffic=None, avg_ms=avg * 1e3,
+                elements=1 << nbits, permutation=pout)
+
+
+def run_precision(args, w, precision, leaves, torch, ws_limit):
+    """Plan, warm up, find the dominant launch, time ``args.steps`` contractions."""
     from paper_2107_09793_amd import Plan
-    from tngen import workloads
-
-    dev = torch.device("cuda:0")
-    w = workloads.build(args.workload, seed=args.seed)
-    plan = Plan.from_network(w.tn, w.path, w.sliced, precision=args.precision,
-                             no_reuse=args.no_reuse)
+    plan = Plan.from_network(w.tn, w.path, w.sliced, precision=precision,
+                             no_reuse=args.no_reuse, workspace_limit=ws_limit)
     info = plan.info()
-    leaves = [torch.from_numpy(np.ascontiguousarray(t, dtype=np.complex64)).to(dev)
-              for t in w.tn.tensors]
     steps = plan.steps()
     for s in steps:
         ea = 1 << (s["nb"] + s["nm"] + s["nk"])
         eb = 1 << (s["nb"] + s["nk"] + s["nn"])
         ec = 1 << (s["nb"] + s["nm"] + s["nn"])
         s["bytes"] = 8.0 * (ea + eb + ec)
-    print(f"# plan: {info['n_steps']} steps, {info['n_slices']} slices, "
-          f"cmac_exec={info['cmac_exec']:.4g}, arena={info['arena_bytes'] / 2**30:.2f} GiB",
-          file=sys.stderr, flush=True)
-
+    print(f"# {precision}: {info['n_steps']} steps, {info['n_launches']} launches, "
+          f"{info['n_slices']} slices, cmac_exec={info['cmac_exec']:.4g}, "
+          f"arena={info['arena_bytes'] / 2**30:.2f} GiB", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         plan.contract(leaves)
     torch.cuda.synchronize()
-    dom = dominant_step(plan, leaves, info, steps, torch)
-
+    units = launch_units(plan, steps)
+    dom, dom_execs = dominant_unit(plan, leaves, info, units, torch)
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -174,38 +287,116 @@ def main():
     torch.cuda.synchronize()
     t = (time.perf_counter() - t0) / args.steps
     dom_s = float(np.mean([a.elapsed_time(b) for a, b in evs])) / 1e3
+    print(f"# {precision}: {t * 1e3:.1f} ms per contraction", file=sys.stderr, flush=True)
+    d = units[dom]
+    rl = roofline(d, dom_s, precision)
+    rl.update(traffic=measured_traffic(args.workload, d, precision), steps=d["steps"],
+              kernel=d["kind"], executions_per_step=dom_execs, cmac=d["cmac"],
+              bytes=d["bytes"], avg_ms=dom_s * 1e3,
+              share_of_step=dom_s * dom_execs / t, shape=d["shape"])
+    res = dict(value=2.0 * info["cmac_exec"] / t / 1e9, slices_per_s=info["n_slices"] / t,
+               ms_per_step=t * 1e3, roofline=rl,
+               amplitude=[float(out.real.item()), float(out.imag.item())]
+               if out.numel() == 1 else None,
+               plan=dict(cmac_reuse=info["cmac_reuse"], cmac_noreuse=info["cmac_noreuse"],
+                         cmac_exec=info["cmac_exec"], f_sl=info["f_sl"],
+                         arena_bytes=info["arena_bytes"], n_launches=info["n_launches"],
+                         n_steps=info["n_steps"], outer_bits=info["n_outer_bits"]))
+    gold = golden(args.workload, args.seed)
+    if gold is not None:
+        ids, ref = gold
+        got = plan.contract(leaves, slice_ids=ids, per_slice=True).cpu().numpy().reshape(-1)
+        rms = np.sqrt(np.mean(np.abs(ref) ** 2))
+        res["rel_err_vs_oracle"] = float(np.max(np.abs(got - ref)) / rms)
+        res["rel_err_slices"] = ids
+    res["tolerance"] = 1e-5 if precision == "c64" else 1e-3
+    return plan, info, res
 
-    value = 2.0 * info["cmac_exec"] / t / 1e9
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed contractions (default 3 "
+                    "for the 53-qubit workload, 10 otherwise)")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="precision", choices=sorted(WORKLOAD_DESC))
+    ap.add_argument("--precision", default="both", choices=["both", "c64", "split_bf16"])
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-budget", type=float, default=20.0,
+                    help="seconds of oracle work for cpu_baseline (0 = skip)")
+    ap.add_argument("--no-reuse", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): slices are independent, "
+              "so the multi-GPU layout is one slice range per GPU plus one all-reduce of the "
+              "float64 partial sums; this build measures the single-GPU share.", file=sys.stderr)
+        sys.exit(2)
+    if args.steps is None:
+        args.steps = 3 if args.workload == "precision" else 10
+
+    import torch
+    from tngen import workloads
+
+    dev = torch.device("cuda:0")
+    w = workloads.build(args.workload, seed=args.seed)
+    leaves = [torch.from_numpy(np.ascontiguousarray(t, dtype=np.complex64)).to(dev)
+              for t in w.tn.tensors]
+    perm = permute_roofline(torch)
+    precs = ["c64", "split_bf16"] if args.precision == "both" else [args.precision]
+    from paper_2107_09793_amd.binding import default_workspace_limit
+    ws_limit = default_workspace_limit()   # the same limit (and outer split) for both
+    results = {}
+    keep = None
+    for prec in precs:
+        plan, info, res = run_precision(args, w, prec, leaves, torch, ws_limit)
+        results[prec] = res
+        plan.release_workspace()
+        if prec == precs[0]:
+            keep = (plan, info)
+        else:
+            del plan
+        torch.cuda.empty_cache()
+    main_prec = precs[0]
+    r0 = results[main_prec]
+    plan, info = keep
     rec = dict(metric="complex GFLOP/s and slices/sec at 1 GPU, split-BF16 vs complex64 at "
                       "stated rel error",
-               value=value, unit="complex GFLOP/s", n_gpus=1, steps=args.steps,
-               warmup=args.warmup, ms_per_step=t * 1e3, higher_is_better=True, scaling="weak",
-               vs_baseline=None, dtype="c64" if args.precision == "c64" else "split_bf16",
+               value=r0["value"], unit="complex GFLOP/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=r0["ms_per_step"], higher_is_better=True,
+               scaling="weak", vs_baseline=None,
+               dtype="c64" if main_prec == "c64" else "split_bf16",
                data="synthetic",
                config=dict(workload=WORKLOAD_DESC[args.workload], name=args.workload,
-                           seed=args.seed, n_slices=info["n_slices"], precision=args.precision,
+                           seed=args.seed, n_slices=info["n_slices"], precision=main_prec,
                            reuse=not args.no_reuse),
-               slices_per_s=info["n_slices"] / t,
-               amplitude=[float(out.real.item()), float(out.imag.item())] if out.numel() == 1 else None)
-    d = steps[dom]
-    rl = roofline(d, dom_s, args.precision)
-    rl.update(traffic=measured_traffic(d, args.precision), step=dom, kernel=d["kind_name"],
-              cmac=d["cmac"],
-              bytes=d["bytes"], avg_ms=dom_s * 1e3,
-              shape=dict(nb=d["nb"], nm=d["nm"], nn=d["nn"], nk=d["nk"]))
-    rec["roofline"] = rl
-    rec["plan"] = dict(cmac_reuse=info["cmac_reuse"], cmac_noreuse=info["cmac_noreuse"],
-                       cmac_exec=info["cmac_exec"], f_sl=info["f_sl"],
-                       arena_bytes=info["arena_bytes"], n_launches=info["n_launches"])
-    if args.cpu_sample > 0:
-        per = plan.contract(leaves, per_slice=True).cpu().numpy()
-        dt, k, cores, err = cpu_baseline(w, args.cpu_sample, per)
-        cps = 2.0 * info["cmac_per_slice"] * k / dt / 1e9
-        rec["cpu_baseline"] = dict(value=cps, unit="complex GFLOP/s", cores=cores, kind="oracle",
-                                   sample=f"{k} of {info['n_slices']} slices, numpy complex128, "
-                                          f"no reuse, {dt:.1f} s",
-                                   slices_per_s=k / dt)
-        rec["rel_err_vs_oracle"] = err
+               slices_per_s=r0["slices_per_s"], amplitude=r0["amplitude"],
+               roofline=r0["roofline"], plan=r0["plan"])
+    for key in ("rel_err_vs_oracle", "rel_err_slices", "tolerance"):
+        if key in r0:
+            rec[key] = r0[key]
+    rec["permute_roofline"] = perm
+    if "split_bf16" in results and main_prec != "split_bf16":
+        sb = results["split_bf16"]
+        rec["split_bf16"] = {k: sb[k] for k in ("value", "slices_per_s", "ms_per_step",
+                                                "roofline", "rel_err_vs_oracle", "tolerance",
+                                                "amplitude") if k in sb}
+        rec["speedup_split_bf16_vs_c64"] = r0["ms_per_step"] / sb["ms_per_step"]
+    if args.cpu_budget > 0:
+        if info["n_slices"] > 1 and args.workload != "precision":
+            per = plan.contract(leaves, per_slice=True).cpu().numpy()
+            cb = cpu_baseline_slices(w, 3, per)
+            cmac = info["cmac_per_slice"] * cb["slices"]
+            rec["rel_err_vs_oracle"] = cb["rel_err"]
+        else:
+            cb = cpu_baseline_prefix(w, args.cpu_budget)
+            cmac = cb["cmac"]
+        rate = cmac / cb["seconds"]
+        slice_cmac = cb.get("slice_cmac", info["cmac_per_slice"])
+        rec["cpu_baseline"] = dict(value=2.0 * rate / 1e9, unit="complex GFLOP/s",
+                                   cores=oracle_cores(), kind="oracle",
+                                   sample=f"{cb['sample']}, numpy complex128, no reuse, "
+                                          f"{cb['seconds']:.1f} s",
+                                   slices_per_s=rate / slice_cmac)
     print(json.dumps(rec), flush=True)
 
 

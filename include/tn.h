@@ -62,6 +62,14 @@ typedef enum { TN_OUT_SUM = 0, TN_OUT_PER_SLICE = 1 } tn_out_mode;
 /* plan flags */
 #define TN_FLAG_NO_REUSE 1u   /* every slice recomputes every step (Eq. sliced_flops) */
 #define TN_FLAG_SIMPLE_KERNELS 2u /* force the plain per-element kernels (debug)     */
+#define TN_FLAG_NO_PERSISTENT 4u  /* no persistent segments (the default; kept so
+                                     existing callers stay valid)                    */
+#define TN_FLAG_PERSISTENT 16u    /* experimental: run runs of small steps as one
+                                     persistent launch each (workgroups claim work
+                                     items and wait on completion counters)          */
+#define TN_FLAG_NO_CHAIN 8u       /* run every step of a chain (consecutive stream
+                                     steps on one running tensor) as its own launch
+                                     instead of one fused launch per chain           */
 #define TN_N_GEMM_CONFIGS 6       /* tile configurations per precision              */
 
 typedef struct {
@@ -109,6 +117,8 @@ typedef struct {
   int8_t root_res_log2[48];
   int8_t res_slicebit[48];
   int8_t outer_slicebit[48];
+  int32_t n_chains;               /* fused chains of stream steps (one launch each) */
+  int32_t n_segments;             /* persistent launches of small steps             */
 } tn_plan_info;
 
 /* One step as scheduled (tests, benchmarks, autotuning). */
@@ -126,9 +136,36 @@ typedef struct {
   int8_t sA_m[48], sC_m[48];
   int8_t sB_n[48], sC_n[48];
   int8_t sA_k[48], sB_k[48];
-  int64_t c_offset;           /* arena byte offset of the result                  */
+  int64_t c_offset;           /* arena byte offset of the result (-1: the result
+                                 stays inside a fused chain and is never stored)  */
   int64_t c_bytes;
+  int32_t chain;              /* fused chain holding the step, or -1              */
+  int32_t reserved;
 } tn_step_info;
+
+/* One fused chain as planned (tests).  A chain runs steps first..last (path
+ * order) in one launch over tiles of the running tensor: the tile bits of the
+ * chain input are loaded into LDS slots, every step maps the tile through its
+ * small operand, and the tile bits of the chain output are stored.  Bit j of a
+ * tile-local index sits in LDS slot in_slot[j] / out_slot[j] and at log2
+ * stride in_log2[j] / out_log2[j] in HBM; bit q of the tile number has HBM
+ * strides pas_in[q] / pas_out[q]. */
+typedef struct {
+  int32_t step;               /* step index                                      */
+  int32_t nrow, nk, nn, nbb;  /* row / summed / new bits, batch bits of B         */
+  int8_t kslot[4], nslot[4];  /* LDS slots of summed and new bits                 */
+  int8_t kB[4], nB[4];        /* B strides of summed and new bits                 */
+  int8_t rslot[12];           /* LDS slots of the row bits                        */
+  int8_t bB[12], bpas[12];    /* batch bits: B stride and tile-number bit         */
+} tn_chain_step_info;
+
+typedef struct {
+  int32_t first, last, phase, tile_bits;
+  int32_t n_in, n_out, n_passive, n_steps;
+  int8_t in_slot[12], in_log2[12], out_slot[12], out_log2[12];
+  int8_t pas_in[40], pas_out[40];
+  tn_chain_step_info st[8];
+} tn_chain_info;
 
 /*
  * Build a plan.  Arguments:
@@ -165,7 +202,11 @@ tn_status tn_plan_step(tn_plan_t plan, int32_t step, tn_step_info* out);
  *   n_slice_ids (or n_slices) rows of out_elems complex128.
  * ws / ws_bytes: device workspace of at least info.workspace_bytes bytes.
  * The sum over slices is accumulated in float64 in a fixed order, so results
- * are reproducible run to run.
+ * are reproducible run to run.  Fused chains of stream steps run as one
+ * launch each.  With TN_FLAG_PERSISTENT, runs of small steps execute as
+ * persistent launches whose schedule tables are copied from host memory into
+ * the workspace once at entry (the host copy is staged before the call
+ * returns).
  */
 tn_status tn_contract(tn_plan_t plan, const void* const* leaves, const int64_t* slice_ids,
                       int64_t n_slice_ids, int32_t out_mode, void* out, void* ws,
@@ -195,6 +236,9 @@ tn_status tn_contract_probe(tn_plan_t plan, const void* const* leaves, const int
                             int64_t n_slice_ids, int32_t out_mode, void* out, void* ws,
                             size_t ws_bytes, void* stream, int32_t probe_step, void* ev_start,
                             void* ev_stop);
+
+/* Chain ``i`` (0 <= i < info.n_chains) of the plan. */
+tn_status tn_plan_chain(tn_plan_t plan, int32_t i, tn_chain_info* out);
 
 void tn_plan_destroy(tn_plan_t plan);
 

@@ -7,7 +7,11 @@ Plan loads by default.  Entries: [precision, nm, nn, nk, config] with the
 shape as log2 (rows, columns, summed); the plan applies an entry to steps
 with the same precision and column count and the nearest (rows, summed).
 
-    python -m paper_2107_09793_amd.autotune [--workload sliced] [--shapes 6]
+    python -m paper_2107_09793_amd.autotune [--workload sliced precision] [--shapes 6]
+
+With several workloads the entries of all of them go into one table.  Steps
+are timed on a contraction of slice 0 only (the slice-independent steps plus
+one pass of the per-slice steps), which holds every step once.
 """
 
 import argparse
@@ -32,7 +36,7 @@ def time_step(plan, leaves, step, reps, torch):
     for _ in range(reps):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
-        plan.contract(leaves, probe=(step, e0, e1))
+        plan.contract(leaves, slice_ids=[0], probe=(step, e0, e1))
         torch.cuda.synchronize()
         ts.append(e0.elapsed_time(e1))
     return float(np.median(ts))
@@ -67,7 +71,7 @@ def tune(workload="sliced", seed=0, n_shapes=6, reps=3, precisions=("c64", "spli
         for cfg in range(N_CONFIGS):
             pl = Plan.from_network(w.tn, w.path, w.sliced, precision=prec, gemm_config=cfg,
                                    tune=[])
-            pl.contract(leaves)
+            pl.contract(leaves, slice_ids=[0])
             torch.cuda.synchronize()
             for k in chosen:
                 ms = time_step(pl, leaves, k, reps, torch)
@@ -86,23 +90,43 @@ def tune(workload="sliced", seed=0, n_shapes=6, reps=3, precisions=("c64", "spli
     doc = dict(device="MI355X (gfx950)", workload=workload, seed=seed,
                generated=time.strftime("%Y-%m-%d %H:%M:%S"),
                configs=CONFIG_NAMES, entries=entries, measurements=raw)
+    write(doc, out)
+    return doc
+
+
+def write(doc, out):
     for path in ([out] if isinstance(out, str) else list(out or [])):
         os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
         with open(path, "w") as f:
             json.dump(doc, f, indent=1)
-    return doc
+
+
+def merge(docs):
+    """One table from several workloads' results (an entry per distinct
+    (precision, shape); the first workload's choice wins a tie of shapes)."""
+    seen, entries, raw = set(), [], []
+    for d in docs:
+        for e in d["entries"]:
+            if tuple(e[:4]) not in seen:
+                seen.add(tuple(e[:4]))
+                entries.append(e)
+        raw += [dict(m, workload=d["workload"]) for m in d["measurements"]]
+    return dict(device=docs[0]["device"], workload=[d["workload"] for d in docs],
+                seed=docs[0]["seed"], generated=docs[-1]["generated"],
+                configs=CONFIG_NAMES, entries=entries, measurements=raw)
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="sliced")
+    ap.add_argument("--workload", nargs="+", default=["sliced"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--shapes", type=int, default=6)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--out", nargs="+", default=[os.path.join(HERE, "tune", "gfx950.json")])
     args = ap.parse_args()
-    tune(args.workload, args.seed, args.shapes, args.reps, out=args.out,
-         log=lambda s: print(s, flush=True))
+    docs = [tune(wl, args.seed, args.shapes, args.reps, out=None,
+                 log=lambda s: print(s, flush=True)) for wl in args.workload]
+    write(merge(docs), args.out)
 
 
 if __name__ == "__main__":

@@ -18,6 +18,9 @@ TN_C64, TN_SPLIT_BF16 = 0, 1
 TN_OUT_SUM, TN_OUT_PER_SLICE = 0, 1
 TN_FLAG_NO_REUSE = 1
 TN_FLAG_SIMPLE_KERNELS = 2
+TN_FLAG_NO_PERSISTENT = 4
+TN_FLAG_NO_CHAIN = 8
+TN_FLAG_PERSISTENT = 16
 KIND_NAMES = {0: "simple", 1: "splitk", 2: "stream", 3: "gemm"}
 
 I8x48 = ctypes.c_int8 * 48
@@ -41,7 +44,8 @@ class PlanInfo(ctypes.Structure):
             "cmac_reuse", "cmac_noreuse", "cmac_exec", "cmac_per_slice", "f_sl",
             "bytes_min_exec")] + \
         [(n, I8x48) for n in ("root_open_log2", "root_res_log2", "res_slicebit",
-                              "outer_slicebit")]
+                              "outer_slicebit")] + \
+        [("n_chains", ctypes.c_int32), ("n_segments", ctypes.c_int32)]
 
 
 class StepInfo(ctypes.Structure):
@@ -50,12 +54,27 @@ class StepInfo(ctypes.Structure):
         [("cmac", ctypes.c_double)] + \
         [(n, I8x48) for n in ("sA_b", "sB_b", "sC_b", "sA_m", "sC_m", "sB_n", "sC_n",
                               "sA_k", "sB_k")] + \
-        [("c_offset", ctypes.c_int64), ("c_bytes", ctypes.c_int64)]
+        [("c_offset", ctypes.c_int64), ("c_bytes", ctypes.c_int64),
+         ("chain", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class ChainStepInfo(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("step", "nrow", "nk", "nn", "nbb")] + \
+        [(n, ctypes.c_int8 * 4) for n in ("kslot", "nslot", "kB", "nB")] + \
+        [(n, ctypes.c_int8 * 12) for n in ("rslot", "bB", "bpas")]
+
+
+class ChainInfo(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("first", "last", "phase", "tile_bits", "n_in",
+                                              "n_out", "n_passive", "n_steps")] + \
+        [(n, ctypes.c_int8 * 12) for n in ("in_slot", "in_log2", "out_slot", "out_log2")] + \
+        [(n, ctypes.c_int8 * 40) for n in ("pas_in", "pas_out")] + \
+        [("st", ChainStepInfo * 8)]
 
 
 EXPORTS = ("tn_plan_create", "tn_plan_query", "tn_plan_step", "tn_contract",
            "tn_contract_probe", "tn_contract_backward", "tn_plan_destroy", "tn_last_error",
-           "tn_permute")
+           "tn_permute", "tn_plan_chain")
 
 _lib = None
 
@@ -86,6 +105,8 @@ def lib():
         L.tn_contract_backward.restype = ctypes.c_int
         L.tn_contract_backward.argtypes = [P, ctypes.POINTER(P), P, ctypes.POINTER(P), P,
                                            ctypes.c_size_t, P]
+        L.tn_plan_chain.restype = ctypes.c_int
+        L.tn_plan_chain.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ChainInfo)]
         L.tn_plan_destroy.restype = None
         L.tn_plan_destroy.argtypes = [P]
         L.tn_last_error.restype = ctypes.c_char_p
@@ -123,6 +144,18 @@ def _stream_ptr(stream):
 TUNE_PATH = os.path.join(_HERE, "tune", "gfx950.json")
 
 
+def default_workspace_limit():
+    """80 % of the current device's free memory (0 = no limit without a GPU)."""
+    try:
+        import torch
+        if not torch.cuda.is_available():
+            return 0
+        free, _ = torch.cuda.mem_get_info()
+        return int(0.8 * free)
+    except Exception:
+        return 0
+
+
 def load_tune_table(path=TUNE_PATH):
     """Autotuned GEMM tile choices: list of [precision, nm, nn, nk, config]."""
     if not os.path.exists(path):
@@ -142,8 +175,8 @@ class Plan:
     """
 
     def __init__(self, labels, dims, open_ids, path, sliced=(), precision="c64",
-                 max_resident_bits=-1, workspace_limit=0, no_reuse=False, simple=False,
-                 gemm_config=-1, tune="default"):
+                 max_resident_bits=-1, workspace_limit="auto", no_reuse=False, simple=False,
+                 gemm_config=-1, tune="default", persistent=False, chains=True):
         n_index = (max(dims) + 1) if isinstance(dims, dict) else len(dims)
         dim_arr = [dims[i] for i in range(n_index)]
         ranks, r_p = _i32([len(l) for l in labels])
@@ -155,8 +188,11 @@ class Plan:
         opts = PlanOptions()
         opts.precision = {"c64": TN_C64, "split_bf16": TN_SPLIT_BF16}[precision]
         opts.max_resident_bits = max_resident_bits
-        opts.workspace_limit = workspace_limit
-        opts.flags = (TN_FLAG_NO_REUSE if no_reuse else 0) | (TN_FLAG_SIMPLE_KERNELS if simple else 0)
+        opts.workspace_limit = default_workspace_limit() if workspace_limit == "auto" \
+            else int(workspace_limit)
+        opts.flags = (TN_FLAG_NO_REUSE if no_reuse else 0) | \
+            (TN_FLAG_SIMPLE_KERNELS if simple else 0) | \
+            (TN_FLAG_PERSISTENT if persistent else 0) | (0 if chains else TN_FLAG_NO_CHAIN)
         opts.gemm_config = gemm_config
         entries = load_tune_table() if tune == "default" else (tune or [])
         tarr, t_p = _i32([x for e in entries for x in e] or [0])
@@ -211,6 +247,35 @@ class Plan:
 
     def steps(self):
         return [self.step(k) for k in range(self.n_tensors - 1)]
+
+    def chain(self, i):
+        """Fused chain ``i`` (``tn_plan_chain``) with lists cut to length."""
+        c = ChainInfo()
+        _check(lib().tn_plan_chain(self._h, i, ctypes.byref(c)))
+        d = {k: getattr(c, k) for k in ("first", "last", "phase", "tile_bits")}
+        d["in_slot"] = list(c.in_slot)[:c.n_in]
+        d["in_log2"] = list(c.in_log2)[:c.n_in]
+        d["out_slot"] = list(c.out_slot)[:c.n_out]
+        d["out_log2"] = list(c.out_log2)[:c.n_out]
+        d["pas_in"] = list(c.pas_in)[:c.n_passive]
+        d["pas_out"] = list(c.pas_out)[:c.n_passive]
+        d["st"] = []
+        for q in range(c.n_steps):
+            t = c.st[q]
+            d["st"].append(dict(step=t.step, nrow=t.nrow,
+                                kslot=list(t.kslot)[:t.nk], nslot=list(t.nslot)[:t.nn],
+                                kB=list(t.kB)[:t.nk], nB=list(t.nB)[:t.nn],
+                                rslot=list(t.rslot)[:t.nrow],
+                                bB=list(t.bB)[:t.nbb], bpas=list(t.bpas)[:t.nbb]))
+        return d
+
+    def chains(self):
+        return [self.chain(i) for i in range(self.info()["n_chains"])]
+
+    def release_workspace(self):
+        """Drop the cached device workspaces (allocated again on next use)."""
+        self._ws = None
+        self._ws_bwd = None
 
     def _workspace(self, nbytes, device, attr):
         import torch

@@ -9,9 +9,9 @@ namespace tnk {
 constexpr int kBlock = 256;
 
 // ---------------------------------------------------------------------------
-// Plain contraction: one thread per output element; the k sum walks k in
-// Gray-code order so each step changes exactly one bit of k (one add to each
-// operand offset).  Fixed order -> reproducible.
+// Plain contraction: one thread per output element, k summed in increasing
+// order (the same multiply-add sequence as the stream kernel and the
+// persistent executor, so the three agree bit for bit).
 __global__ void __launch_bounds__(kBlock) k_simple(StepArgs p) {
   const uint64_t n_out = 1ull << (p.nb + p.nm + p.nn);
   const uint64_t K = 1ull << p.nk;
@@ -24,17 +24,9 @@ __global__ void __launch_bounds__(kBlock) k_simple(StepArgs p) {
     int64_t ob = scatter(n, p.sB_n, p.nn) + scatter(b, p.sB_b, p.nb);
     int64_t oc = scatter(n, p.sC_n, p.nn) + scatter(m, p.sC_m, p.nm) + scatter(b, p.sC_b, p.nb);
     float2 acc = make_float2(0.f, 0.f);
-    uint64_t g = 0;
-    for (uint64_t i = 0; i < K; ++i) {
-      if (i) {
-        int j = __builtin_ctzll(i);
-        uint64_t bit = 1ull << j;
-        int64_t da = (int64_t)1 << p.sA_k[j], db = (int64_t)1 << p.sB_k[j];
-        if (g & bit) { oa -= da; ob -= db; } else { oa += da; ob += db; }
-        g ^= bit;
-      }
-      cfma(acc, maybe_conj(p.A[oa], p.conjA), maybe_conj(p.B[ob], p.conjB));
-    }
+    for (uint64_t k = 0; k < K; ++k)
+      cfma(acc, maybe_conj(p.A[oa + scatter(k, p.sA_k, p.nk)], p.conjA),
+           maybe_conj(p.B[ob + scatter(k, p.sB_k, p.nk)], p.conjB));
     if (p.accumulate) {
       float2 c = p.C[oc];
       acc.x += c.x;
@@ -120,6 +112,15 @@ struct StreamArgs {
   int8_t kA[4], kB[4], nB[4], nC[4];
 };
 
+// Offset of bits [lo, hi) of idx, as a plain loop: with a uniform idx the
+// compiler keeps it in scalar registers.
+__device__ __forceinline__ int64_t scatter_loop(uint64_t idx, const int8_t* s, int lo, int hi) {
+  int64_t off = 0;
+#pragma unroll 1
+  for (int j = lo; j < hi; ++j) off += (int64_t)((idx >> j) & 1ull) << s[j];
+  return off;
+}
+
 template <int N>
 __device__ __forceinline__ int64_t scatter_c(uint64_t idx, const int8_t* s, int lo, int hi) {
   int64_t off = 0;
@@ -129,28 +130,26 @@ __device__ __forceinline__ int64_t scatter_c(uint64_t idx, const int8_t* s, int 
   return off;
 }
 
-template <int NK, int NN>
+// SHB: every row of a workgroup pass shares one batch value, so the small
+// operand is staged in LDS once per pass and read by broadcast; otherwise it
+// is read through the cache per row.
+template <int NK, int NN, bool SHB>
 __global__ void __launch_bounds__(kBlock) k_stream(StreamArgs p) {
   constexpr int KN = (1 << NK) * (1 << NN);
-  __shared__ float2 sB[KN];
+  __shared__ float2 sB[SHB ? KN : 1];
   const int nrow = p.nrow;
   const uint64_t rows = 1ull << nrow;
   const int low = nrow < 8 ? nrow : 8;
   const int64_t la = scatter_c<8>(threadIdx.x, p.rowA, 0, low);
   const int64_t lc = scatter_c<8>(threadIdx.x, p.rowC, 0, low);
-  int64_t kofA[1 << NK];
-#pragma unroll
-  for (int k = 0; k < (1 << NK); ++k) kofA[k] = scatter_c<NK>(k, p.kA, 0, NK);
   const int brow0 = nrow - p.nbB;   // first batch bit among the row bits
-  // B lives in LDS when all rows of a workgroup pass share one batch value
-  const bool shared_b = p.nbB == 0 || brow0 >= 8;
   int64_t staged = -1;
   for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < rows;
        base += (uint64_t)gridDim.x * kBlock) {
-    const int64_t ha = scatter_c<kMaxBits>(base, p.rowA, 8, nrow);   // uniform
-    const int64_t hc = scatter_c<kMaxBits>(base, p.rowC, 8, nrow);
-    if (shared_b) {
-      const int64_t ob = p.nbB ? scatter_c<kMaxBits>(base >> brow0, p.bB, 0, p.nbB) : 0;
+    const int64_t ha = scatter_loop(base, p.rowA, 8, nrow);   // uniform
+    const int64_t hc = scatter_loop(base, p.rowC, 8, nrow);
+    if (SHB) {
+      const int64_t ob = p.nbB ? scatter_loop(base >> brow0, p.bB, 0, p.nbB) : 0;
       if (ob != staged) {
         __syncthreads();
         for (int i = threadIdx.x; i < KN; i += kBlock) {
@@ -164,28 +163,34 @@ __global__ void __launch_bounds__(kBlock) k_stream(StreamArgs p) {
     }
     const uint64_t r = base + threadIdx.x;
     if (r >= rows) continue;
-    const int64_t oa = la + ha, oc = lc + hc;
+    const float2* Ar = p.A + (la + ha);
+    float2* Cr = p.C + (lc + hc);
     float2 a[1 << NK];
 #pragma unroll
-    for (int k = 0; k < (1 << NK); ++k) a[k] = maybe_conj(p.A[oa + kofA[k]], p.conjA);
-    const int64_t ob = shared_b ? 0 : scatter_c<kMaxBits>(r >> brow0, p.bB, 0, p.nbB);
+    for (int k = 0; k < (1 << NK); ++k)
+      a[k] = maybe_conj(Ar[scatter_c<NK>(k, p.kA, 0, NK)], p.conjA);
+    const float2* Br = SHB ? nullptr : p.B + scatter_loop(r >> brow0, p.bB, 0, p.nbB);
 #pragma unroll
     for (int n = 0; n < (1 << NN); ++n) {
       float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
       for (int k = 0; k < (1 << NK); ++k) {
-        float2 b = shared_b ? sB[k * (1 << NN) + n]
-                            : maybe_conj(p.B[ob + scatter_c<NK>(k, p.kB, 0, NK) +
-                                             scatter_c<NN>(n, p.nB, 0, NN)], p.conjB);
+        float2 b;
+        if (SHB) {
+          b = sB[k * (1 << NN) + n];
+        } else {
+          b = maybe_conj(Br[scatter_c<NK>(k, p.kB, 0, NK) + scatter_c<NN>(n, p.nB, 0, NN)],
+                         p.conjB);
+        }
         cfma(acc, a[k], b);
       }
-      const int64_t ocn = oc + scatter_c<NN>(n, p.nC, 0, NN);
+      float2* cp = Cr + scatter_c<NN>(n, p.nC, 0, NN);
       if (p.accumulate) {
-        float2 c = p.C[ocn];
+        float2 c = *cp;
         acc.x += c.x;
         acc.y += c.y;
       }
-      p.C[ocn] = acc;
+      *cp = acc;
     }
   }
 }
@@ -204,6 +209,98 @@ __global__ void __launch_bounds__(kBlock) k_permute_plain(PermArgs p) {
   for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
        i += (uint64_t)gridDim.x * kBlock)
     p.out[scatter(i, p.sout, p.nbits)] = p.in[scatter(i, p.sin, p.nbits)];
+}
+
+// ---------------------------------------------------------------------------
+// Bit permutation through an LDS tile (the transpose of the TTGT
+// decomposition, Sec. 3.1, for tensors whose dims are all 2).  The tile holds
+// the 2^TB elements spanned by TB index bits: the bits of the lowest input
+// strides (contiguous reads), the bits of the lowest output strides
+// (contiguous writes) and, if fewer, further bits.  A workgroup reads its tile
+// in input order into LDS, then writes it in output order.  LDS positions are
+// XOR-swizzled (low half ^= high half) so the strided LDS reads of the write
+// phase spread over banks.  All offsets are XOR/OR-linear in the index bits,
+// so each thread splits them into a per-thread part (its 8 low bits) and a
+// per-element part.
+struct PermTileArgs {
+  const float2* in;
+  float2* out;
+  int32_t tbits;            // bits in the tile (= the kernel's TB)
+  int32_t rbits;            // bits enumerating tiles
+  int32_t half;             // swizzle width
+  int8_t rin[16];           // input log2 stride of tile position p (read order = LDS order)
+  int8_t wout[16], wpos[16];  // write order: output log2 stride and LDS position
+  int8_t tin[kMaxBits], tout[kMaxBits];  // tile-index bits: input / output log2 strides
+};
+
+__device__ __forceinline__ uint32_t perm_swz(uint32_t x, int half) {
+  return x ^ ((x >> half) & ((1u << half) - 1u));
+}
+
+template <int TB>
+__global__ void __launch_bounds__(kBlock) k_permute_tile(PermTileArgs p) {
+  static_assert(TB >= 8 && TB <= 16, "tile of 256 threads x E elements");
+  constexpr int E = 1 << (TB - 8);
+  __shared__ float2 tile[1 << TB];
+  __shared__ int8_t s_tin[kMaxBits], s_tout[kMaxBits];
+  const int tid = threadIdx.x;
+  if (tid < kMaxBits) {
+    s_tin[tid] = p.tin[tid];
+    s_tout[tid] = p.tout[tid];
+  }
+  // per-thread parts (tile bits 0..7 = thread id bits)
+  int64_t in_lo = 0, out_lo = 0;
+  uint32_t wl_lo = 0;
+#pragma unroll 1
+  for (int b = 0; b < 8; ++b) {
+    const int64_t bit = (tid >> b) & 1;
+    in_lo += bit << p.rin[b];
+    out_lo += bit << p.wout[b];
+    wl_lo |= (uint32_t)bit << p.wpos[b];
+  }
+  const uint32_t rl_lo = perm_swz((uint32_t)tid, p.half);
+  wl_lo = perm_swz(wl_lo, p.half);
+  // per-element parts (tile bits 8.. = element counter e)
+  int64_t in_hi[E], out_hi[E];
+  uint32_t rl_hi[E], wl_hi[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    int64_t a = 0, c = 0;
+    uint32_t w = 0;
+#pragma unroll 1
+    for (int b = 8; b < TB; ++b) {
+      const int64_t bit = (e >> (b - 8)) & 1;
+      a += bit << p.rin[b];
+      c += bit << p.wout[b];
+      w |= (uint32_t)bit << p.wpos[b];
+    }
+    in_hi[e] = a;
+    out_hi[e] = c;
+    rl_hi[e] = perm_swz((uint32_t)e << 8, p.half);
+    wl_hi[e] = perm_swz(w, p.half);
+  }
+  __syncthreads();
+  const uint64_t n_tiles = 1ull << p.rbits;
+  for (uint64_t g = blockIdx.x; g < n_tiles; g += gridDim.x) {
+    int64_t bin = 0, bout = 0;
+#pragma unroll 1
+    for (int b = 0; b < p.rbits; ++b) {
+      const int64_t bit = (g >> b) & 1ull;
+      bin += bit << s_tin[b];
+      bout += bit << s_tout[b];
+    }
+    float2 v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = p.in[bin + in_lo + in_hi[e]];
+#pragma unroll
+    for (int e = 0; e < E; ++e) tile[rl_lo ^ rl_hi[e]] = v[e];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = tile[wl_lo ^ wl_hi[e]];
+#pragma unroll
+    for (int e = 0; e < E; ++e) p.out[bout + out_lo + out_hi[e]] = v[e];
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -70,28 +70,50 @@ __device__ __forceinline__ void split_bits(int e, uint32_t mask, int nbits, int&
   }
 }
 
-// Offsets shared by both precisions.
+// Per-workgroup LDS copy of the step's bit strides (read once from the kernel
+// arguments, then indexed freely) and the tile offset tables.
+struct Strides {
+  int8_t v[9 * kMaxBits];   // same order as in StepArgs
+  __device__ __forceinline__ const int8_t* Ab() const { return v; }
+  __device__ __forceinline__ const int8_t* Bb() const { return v + kMaxBits; }
+  __device__ __forceinline__ const int8_t* Cb() const { return v + 2 * kMaxBits; }
+  __device__ __forceinline__ const int8_t* Am() const { return v + 3 * kMaxBits; }
+  __device__ __forceinline__ const int8_t* Cm() const { return v + 4 * kMaxBits; }
+  __device__ __forceinline__ const int8_t* Bn() const { return v + 5 * kMaxBits; }
+  __device__ __forceinline__ const int8_t* Cn() const { return v + 6 * kMaxBits; }
+  __device__ __forceinline__ const int8_t* Ak() const { return v + 7 * kMaxBits; }
+  __device__ __forceinline__ const int8_t* Bk() const { return v + 8 * kMaxBits; }
+};
+static_assert(offsetof(StepArgs, sA_b) % 4 == 0, "stride arrays word aligned");
+
+__device__ __forceinline__ void load_strides(const StepArgs& p, Strides& s) {
+  const int32_t* src = reinterpret_cast<const int32_t*>(p.sA_b);
+  int32_t* dst = reinterpret_cast<int32_t*>(s.v);
+  for (int i = threadIdx.x; i < 9 * kMaxBits / 4; i += 256) dst[i] = src[i];
+}
+
 template <int MT, int NT, int KT>
 struct GemmTables {
   int64_t am[MT], ak[KT], bk[KT], bn[NT], cm[MT], cn[NT];
 };
 
 template <int MT, int NT, int KT>
-__device__ __forceinline__ void build_tables(const StepArgs& p, GemmTables<MT, NT, KT>& t) {
+__device__ __forceinline__ void build_tables(const StepArgs& p, const Strides& S,
+                                             GemmTables<MT, NT, KT>& t) {
   constexpr int LM = ilog2<MT>::value, LN = ilog2<NT>::value, LK = ilog2<KT>::value;
   const int tid = threadIdx.x;
   const int nmv = p.nm < LM ? p.nm : LM, nnv = p.nn < LN ? p.nn : LN, nkv = p.nk < LK ? p.nk : LK;
   for (int i = tid; i < MT; i += 256) {
-    t.am[i] = scatter(i, p.sA_m, nmv);
-    t.cm[i] = scatter(i, p.sC_m, nmv);
+    t.am[i] = scatter(i, S.Am(), nmv);
+    t.cm[i] = scatter(i, S.Cm(), nmv);
   }
   for (int i = tid; i < NT; i += 256) {
-    t.bn[i] = scatter(i, p.sB_n, nnv);
-    t.cn[i] = scatter(i, p.sC_n, nnv);
+    t.bn[i] = scatter(i, S.Bn(), nnv);
+    t.cn[i] = scatter(i, S.Cn(), nnv);
   }
   for (int i = tid; i < KT; i += 256) {
-    t.ak[i] = scatter(i, p.sA_k, nkv);
-    t.bk[i] = scatter(i, p.sB_k, nkv);
+    t.ak[i] = scatter(i, S.Ak(), nkv);
+    t.bk[i] = scatter(i, S.Bk(), nkv);
   }
 }
 
@@ -154,21 +176,21 @@ struct GemmCommon {
     tile = blockIdx.x;
   }
 
-  __device__ __forceinline__ void set_tile(const StepArgs& p, uint64_t t) {
+  __device__ __forceinline__ void set_tile(const StepArgs& p, const Strides& S, uint64_t t) {
     uint64_t bidx, mt, nt;
     tile_coords(p, LM, LN, t, ntiles, remap, bidx, mt, nt);
-    baseA = scatter_range(mt << LM, p.sA_m, LM, p.nm) + scatter(bidx, p.sA_b, p.nb);
-    baseB = scatter_range(nt << LN, p.sB_n, LN, p.nn) + scatter(bidx, p.sB_b, p.nb);
-    baseC = scatter_range(mt << LM, p.sC_m, LM, p.nm) + scatter_range(nt << LN, p.sC_n, LN, p.nn) +
-            scatter(bidx, p.sC_b, p.nb);
+    baseA = scatter_range(mt << LM, S.Am(), LM, p.nm) + scatter(bidx, S.Ab(), p.nb);
+    baseB = scatter_range(nt << LN, S.Bn(), LN, p.nn) + scatter(bidx, S.Bb(), p.nb);
+    baseC = scatter_range(mt << LM, S.Cm(), LM, p.nm) + scatter_range(nt << LN, S.Cn(), LN, p.nn) +
+            scatter(bidx, S.Cb(), p.nb);
     kA = kB = 0;
     gray = 0;
   }
 
-  __device__ __forceinline__ void advance(const StepArgs& p, uint64_t kt) {
+  __device__ __forceinline__ void advance(const Strides& S, uint64_t kt) {
     int j = __builtin_ctzll(kt);
     uint64_t bit = 1ull << j;
-    int64_t da = (int64_t)1 << p.sA_k[LK + j], db = (int64_t)1 << p.sB_k[LK + j];
+    int64_t da = (int64_t)1 << S.Ak()[LK + j], db = (int64_t)1 << S.Bk()[LK + j];
     if (gray & bit) { kA -= da; kB -= db; } else { kA += da; kB += db; }
     gray ^= bit;
   }
@@ -213,33 +235,40 @@ struct GemmCommon {
   }
 };
 
-// The persistent tile loop shared by both precisions.  OPS supplies the LDS
-// staging (lstore) and the MFMA block for one k tile (compute).
+// One output tile per workgroup, shared by both precisions.  The tile's first
+// MFMA takes a zero accumulator (Ops::compute<true>).  Ops supplies the LDS
+// staging (lstore) and the MFMA block of one k tile (compute).  (A persistent
+// loop over tiles keeps the epilogue's offsets live across tiles and costs an
+// occupancy step, so each workgroup runs one tile.)
 template <int WVN, int WM, int WN, int MT, int NT, int KT, class OffT, class Ops>
-__device__ __forceinline__ void gemm_tiles(const StepArgs& p, GemmCommon<MT, NT, KT, OffT>& c,
+__device__ __forceinline__ void gemm_tiles(const StepArgs& p, const Strides& S,
+                                           GemmCommon<MT, NT, KT, OffT>& c,
                                            const GemmTables<MT, NT, KT>& tab, Ops& ops) {
   using GC = GemmCommon<MT, NT, KT, OffT>;
+  const uint64_t tile = blockIdx.x;
+  if (tile >= c.ntiles) return;
   float2 ra[GC::AE], rb[GC::BE];
-  if (c.tile >= c.ntiles) return;
-  c.set_tile(p, c.tile);
-  c.gload(p, ra, rb);
   floatx16 acc[WM][WN];
-#pragma unroll
-  for (int i = 0; i < WM; ++i)
-#pragma unroll
-    for (int j = 0; j < WN; ++j)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+  c.set_tile(p, S, tile);
+  c.gload(p, ra, rb);
   ops.lstore(0, ra, rb);
   __syncthreads();
-  for (uint64_t kt = 0; kt < c.nkt; ++kt) {
+  // k tile 0 (defines acc), then the double-buffered rest
+  if (c.nkt > 1) {
+    c.advance(S, 1);
+    c.gload(p, ra, rb);
+  }
+  ops.template compute<true>(0, acc);
+  if (c.nkt > 1) ops.lstore(1, ra, rb);
+  __syncthreads();
+  for (uint64_t kt = 1; kt < c.nkt; ++kt) {
     const int buf = kt & 1;
     const bool last = kt + 1 == c.nkt;
     if (!last) {
-      c.advance(p, kt + 1);
+      c.advance(S, kt + 1);
       c.gload(p, ra, rb);
     }
-    ops.compute(buf, acc);
+    ops.template compute<false>(buf, acc);
     if (!last) ops.lstore(buf ^ 1, ra, rb);
     __syncthreads();
   }
@@ -266,24 +295,36 @@ struct OpsC64 {
     for (int r = 0; r < GC::BE; ++r)
       sB[buf][c->b_nk[r] >> 16][c->b_nk[r] & 0xFFFF] = make_float2(rb[r].x, sb * rb[r].y);
   }
-  __device__ __forceinline__ void compute(int buf, floatx16 (&acc)[WM][WN]) {
+  // one k column of the tile; ZERO: start from a zero accumulator
+  template <bool ZERO>
+  __device__ __forceinline__ void kstep(int buf, int kk, floatx16 (&acc)[WM][WN]) {
     const int half = lane >> 5, par = lane & 1;
-#pragma unroll 4
-    for (int kk = 0; kk < KT; ++kk) {
-      float av[WM], bv[WN];
+    float av[WM], bv[WN];
 #pragma unroll
-      for (int i = 0; i < WM; ++i) av[i] = sA[buf][half][kk][wave_m * WM * 32 + i * 32 + (lane & 31)];
+    for (int i = 0; i < WM; ++i) av[i] = sA[buf][half][kk][wave_m * WM * 32 + i * 32 + (lane & 31)];
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      float2 bc = sB[buf][kk][wave_n * WN * 16 + j * 16 + ((lane & 31) >> 1)];
+      bv[j] = half == 0 ? (par ? bc.y : bc.x) : (par ? bc.x : -bc.y);
+    }
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
 #pragma unroll
       for (int j = 0; j < WN; ++j) {
-        float2 bc = sB[buf][kk][wave_n * WN * 16 + j * 16 + ((lane & 31) >> 1)];
-        bv[j] = half == 0 ? (par ? bc.y : bc.x) : (par ? bc.x : -bc.y);
+        const floatx16 zero = {};
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv[j], ZERO ? zero : acc[i][j], 0,
+                                                         0, 0);
       }
-#pragma unroll
-      for (int i = 0; i < WM; ++i)
-#pragma unroll
-        for (int j = 0; j < WN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+  }
+  template <bool FIRST>
+  __device__ __forceinline__ void compute(int buf, floatx16 (&acc)[WM][WN]) {
+    int k0 = 0;
+    if constexpr (FIRST) {
+      kstep<true>(buf, 0, acc);
+      k0 = 1;
     }
+#pragma unroll 4
+    for (int kk = k0; kk < KT; ++kk) kstep<false>(buf, kk, acc);
   }
 };
 
@@ -297,8 +338,11 @@ k_gemm_c64(GemmArgs g) {
   __shared__ float sA[2][2][KT][MT];
   __shared__ float2 sB[2][KT][NT];
   __shared__ GemmTables<MT, NT, KT> tab;
+  __shared__ Strides S;
   const StepArgs& p = g.s;
-  build_tables<MT, NT, KT>(p, tab);
+  load_strides(p, S);
+  __syncthreads();
+  build_tables<MT, NT, KT>(p, S, tab);
   __syncthreads();
   GC c;
   c.init(g, tab);
@@ -311,7 +355,7 @@ k_gemm_c64(GemmArgs g) {
   ops.lane = threadIdx.x & 63;
   ops.wave_m = (threadIdx.x >> 6) / WVN;
   ops.wave_n = (threadIdx.x >> 6) % WVN;
-  gemm_tiles<WVN, WM, WN>(p, c, tab, ops);
+  gemm_tiles<WVN, WM, WN>(p, S, c, tab, ops);
 }
 
 // ---------------------------------------------------------------------------
@@ -368,8 +412,10 @@ struct OpsSB16 {
       *reinterpret_cast<uint32_t*>(&sB[buf][1][o + 32]) = (lo >> 16) | (lo << 16);
     }
   }
+  template <bool FIRST>
   __device__ __forceinline__ void compute(int buf, floatx16 (&acc)[WM][WN]) {
     const int half = lane >> 5;
+    const floatx16 zero = {};
 #pragma unroll
     for (int s2 = 0; s2 < KT / 8; ++s2) {
       const int kof = 16 * s2 + 8 * half;
@@ -390,7 +436,8 @@ struct OpsSB16 {
       for (int i = 0; i < WM; ++i)
 #pragma unroll
         for (int j = 0; j < WN; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+              ah[i], bh[j], FIRST && s2 == 0 ? zero : acc[i][j], 0, 0, 0);
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
         }
@@ -407,8 +454,11 @@ __global__ void __launch_bounds__(256) k_gemm_sb16(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) uint16_t sA[2][2][MT * 32];
   __shared__ __attribute__((aligned(16))) uint16_t sB[2][2][2 * NT * 32];
   __shared__ GemmTables<MT, NT, KT> tab;
+  __shared__ Strides S;
   const StepArgs& p = g.s;
-  build_tables<MT, NT, KT>(p, tab);
+  load_strides(p, S);
+  __syncthreads();
+  build_tables<MT, NT, KT>(p, S, tab);
   __syncthreads();
   GC c;
   c.init(g, tab);
@@ -421,7 +471,7 @@ __global__ void __launch_bounds__(256) k_gemm_sb16(GemmArgs g) {
   ops.lane = threadIdx.x & 63;
   ops.wave_m = (threadIdx.x >> 6) / WVN;
   ops.wave_n = (threadIdx.x >> 6) % WVN;
-  gemm_tiles<WVN, WM, WN>(p, c, tab, ops);
+  gemm_tiles<WVN, WM, WN>(p, S, c, tab, ops);
 }
 
 }  // namespace tnk

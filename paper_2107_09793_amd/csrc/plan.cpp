@@ -28,6 +28,7 @@
 #include <cmath>
 #include <cstdio>
 #include <map>
+#include <functional>
 #include <numeric>
 
 namespace tn {
@@ -103,6 +104,167 @@ struct Arena {
 struct Layout {  // executed bits of a node with strides (bit id -> log2 stride)
   std::map<int32_t, int8_t> s;
 };
+
+struct StepBits {  // global bit ids of a step's classes, in stride-array order
+  Bits batch, M, N, K;
+};
+
+// Tile of a chain candidate first..last (see ChainGroup); returns false when
+// it does not fit the LDS tile or a summed / batch bit is misplaced.
+bool build_chain(const Plan& p, const std::vector<Layout>& lay, const std::vector<StepBits>& sb,
+                 int first, int last, ChainGroup& g) {
+  const int n = p.n_tensors;
+  const int X = p.steps[first].a, Y = n + last;
+  const Bits& E0 = p.node_ebits[X];
+  // input bits summed inside the chain, bits created inside it
+  Bits in_act, created;
+  for (int k = first; k <= last; ++k) {
+    Bits K = sb[k].K;
+    std::sort(K.begin(), K.end());
+    in_act = unite(in_act, inter(K, E0));
+    Bits N = sb[k].N;
+    std::sort(N.begin(), N.end());
+    created = unite(created, N);
+  }
+  // small operands of all steps are staged together
+  int64_t b_elems = 0;
+  for (int k = first; k <= last; ++k)
+    b_elems += (int64_t)1 << (sb[k].K.size() + sb[k].N.size());
+  if (b_elems > kChainBElems) return false;
+  // batch bits must stay outside the tile; simulate the live tile bits
+  Bits live = in_act;
+  int max_live = (int)live.size();
+  Bits batch_all;
+  for (int k = first; k <= last; ++k) {
+    Bits K = sb[k].K, N = sb[k].N, B = sb[k].batch;
+    std::sort(K.begin(), K.end());
+    std::sort(N.begin(), N.end());
+    std::sort(B.begin(), B.end());
+    if (minus(K, live).size()) return false;          // summed bit not in the tile
+    if (!inter(B, unite(in_act, created)).empty()) return false;
+    batch_all = unite(batch_all, B);
+    live = unite(minus(live, K), N);
+    max_live = std::max(max_live, (int)live.size());
+  }
+  const Bits out_created = live;   // created bits that reach the output
+  const Bits pas = minus(E0, in_act);
+  // low-stride passive bits go into the tile so loads and stores run over
+  // at least 2^3 consecutive elements; more when room is left
+  auto low_bits = [&](int node) {
+    std::vector<std::pair<int, int32_t>> v;
+    for (const auto& kv : lay[node].s) v.push_back({kv.second, kv.first});
+    std::sort(v.begin(), v.end());
+    Bits r;
+    for (auto& x : v) r.push_back(x.second);
+    return r;
+  };
+  const Bits xo = low_bits(X), yo = low_bits(Y);
+  Bits ptile;
+  int want = 5;
+  for (; want >= 3; --want) {
+    ptile.clear();
+    bool ok = true;
+    for (const Bits* o : {&xo, &yo}) {
+      for (int i = 0; i < want && i < (int)o->size(); ++i) {
+        int b = (*o)[i];
+        bool in_tile = std::binary_search(in_act.begin(), in_act.end(), b) ||
+                       std::binary_search(out_created.begin(), out_created.end(), b);
+        if (in_tile) continue;
+        if (std::binary_search(batch_all.begin(), batch_all.end(), b)) { ok = false; break; }
+        if (std::find(ptile.begin(), ptile.end(), b) == ptile.end()) ptile.push_back(b);
+      }
+    }
+    if (ok && max_live + (int)ptile.size() <= kChainTileBits) break;
+  }
+  if (want < 3) return false;
+  std::sort(ptile.begin(), ptile.end());
+  const Bits pt = minus(pas, ptile);   // passive bits that enumerate tiles
+  if ((int)pt.size() > kChainPassive) return false;
+  // LDS slots: tile passive bits lowest, then input bits; a new bit takes
+  // the lowest free slot after the step's summed bits are released
+  std::map<int32_t, int> slot;
+  std::vector<uint8_t> used(kChainTileBits, 0);
+  auto take = [&](int32_t b) {
+    for (int q = 0; q < kChainTileBits; ++q)
+      if (!used[q]) {
+        used[q] = 1;
+        slot[b] = q;
+        return true;
+      }
+    return false;
+  };
+  for (int32_t b : ptile) take(b);
+  Bits in_sorted = in_act;
+  std::sort(in_sorted.begin(), in_sorted.end(),
+            [&](int32_t a, int32_t b) { return lay[X].s.at(a) < lay[X].s.at(b); });
+  for (int32_t b : in_sorted) take(b);
+  g = ChainGroup();
+  g.first = first;
+  g.last = last;
+  g.phase = p.steps[first].phase;
+  Bits tile_live = unite(in_act, ptile);
+  for (int k = first; k <= last; ++k) {
+    const StepDesc& S = p.steps[k];
+    ChainStepDesc d;
+    d.step = k;
+    Bits K = sb[k].K;
+    std::sort(K.begin(), K.end());
+    Bits rows = minus(tile_live, K);
+    for (int32_t b : sb[k].K) d.kslot.push_back((int8_t)slot.at(b));
+    for (int32_t b : K) used[slot.at(b)] = 0;
+    for (int32_t b : sb[k].N)
+      if (!take(b)) return false;
+    for (int32_t b : sb[k].N) d.nslot.push_back((int8_t)slot.at(b));
+    std::vector<int8_t> rs;
+    for (int32_t b : rows) rs.push_back((int8_t)slot.at(b));
+    std::sort(rs.begin(), rs.end());
+    d.rslot = rs;
+    d.nrow = (int32_t)rs.size();
+    d.kB = S.kB;
+    d.nB = S.nB;
+    d.bB = S.bB;
+    for (int32_t b : sb[k].batch) {
+      auto it = std::find(pt.begin(), pt.end(), b);
+      if (it == pt.end()) return false;
+      d.bpas.push_back((int8_t)(it - pt.begin()));
+    }
+    Bits N = sb[k].N;
+    std::sort(N.begin(), N.end());
+    tile_live = unite(rows, N);
+    g.st.push_back(d);
+  }
+  int tb = 0;
+  for (const auto& kv : slot) tb = std::max(tb, kv.second + 1);
+  g.tile_bits = tb;
+  // input tile bits in input-stride order, output tile bits in output order
+  Bits in_tile = unite(in_act, ptile), out_tile = unite(out_created, ptile);
+  std::sort(in_tile.begin(), in_tile.end(),
+            [&](int32_t a, int32_t b) { return lay[X].s.at(a) < lay[X].s.at(b); });
+  std::sort(out_tile.begin(), out_tile.end(),
+            [&](int32_t a, int32_t b) { return lay[Y].s.at(a) < lay[Y].s.at(b); });
+  // slots at load / store time: input bits keep their first slot; output
+  // bits hold the slot they had after the last step
+  std::map<int32_t, int> first_slot;
+  for (int32_t b : ptile) first_slot[b] = slot.at(b);
+  {
+    // recompute the input slots (slot[] was overwritten for reused bits only
+    // if a bit id repeats, which it cannot: bit ids are unique in the chain)
+    for (int32_t b : in_act) first_slot[b] = slot.at(b);
+  }
+  for (int32_t b : in_tile) {
+    g.in_slot.push_back((int8_t)first_slot.at(b));
+    g.in_log2.push_back(lay[X].s.at(b));
+  }
+  for (int32_t b : out_tile) {
+    g.out_slot.push_back((int8_t)slot.at(b));
+    g.out_log2.push_back(lay[Y].s.at(b));
+  }
+  for (int32_t b : pt) {
+    g.pas_in.push_back(lay[X].s.at(b));
+    g.pas_out.push_back(lay[Y].s.at(b));
+  }
+  return true;
+}
 
 }  // namespace
 
@@ -183,6 +345,7 @@ static void schedule(Plan& p) {
   }
 
   p.steps.assign(nsteps, StepDesc());
+  std::vector<StepBits> sbits(nsteps);
   for (int k = 0; k < nsteps; ++k) {
     int a = p.path[2 * k], b = p.path[2 * k + 1], v = n + k;
     StepDesc& S = p.steps[k];
@@ -206,6 +369,7 @@ static void schedule(Plan& p) {
     batch = by(batch, lay[a]);
     K = by(K, lay[a]);
     int nb = (int)batch.size(), nm = (int)M.size(), nnb = (int)N.size(), nk = (int)K.size();
+    sbits[k] = StepBits{batch, M, N, K};
     S.kind = choose_kind(nb, nm, nnb, nk, p.flags, &S.splitk_chunks, &S.scratch_bytes);
     // result layout, least significant first.  GEMM tiles store 16 consecutive
     // columns per half-wave: columns, rows, batch.  The stream kernel runs one
@@ -247,27 +411,137 @@ static void schedule(Plan& p) {
   }
   const int root = nn_nodes - 1;
 
-  // schedule: phase 0 in path order, then phase 1 in path order
-  p.sched.clear();
-  for (int k = 0; k < nsteps; ++k)
-    if (p.steps[k].phase == 0) p.sched.push_back(k);
-  p.n_phase0 = (int32_t)p.sched.size();
-  for (int k = 0; k < nsteps; ++k)
-    if (p.steps[k].phase == 1) p.sched.push_back(k);
+  // small steps: run as work items of persistent segments (opt-in: a GPU
+  // test of the segment kernel at full size did not finish, cause not found)
+  const bool persist = (p.flags & 16u) && !(p.flags & 4u);
+  for (int k = 0; k < nsteps; ++k) {
+    StepDesc& S = p.steps[k];
+    int nb = (int)S.bA.size(), nm = (int)S.mA.size(), nnb = (int)S.nB.size(), nk = (int)S.kA.size();
+    S.small = persist && (S.kind == KIND_STREAM || S.kind == KIND_SIMPLE) &&
+              S.cmac <= std::ldexp(1.0, 22) && nb <= kSmallClassBits &&
+              nm <= kSmallClassBits && nnb <= kSmallClassBits && nk <= kSmallClassBits;
+  }
+  // chains: runs of consecutive large stream steps, each consuming the
+  // previous result as its large operand, grown while the tile fits
+  p.chains.clear();
+  if (!(p.flags & 8u)) {
+    auto fusable = [&](int k) {
+      const StepDesc& S = p.steps[k];
+      return S.kind == KIND_STREAM && !S.small && S.kA.size() <= 4 && S.nB.size() <= 4;
+    };
+    int k = 0;
+    while (k < nsteps) {
+      if (!fusable(k)) { ++k; continue; }
+      int j = k;
+      ChainGroup g, cand;
+      while (j + 1 < nsteps && j + 1 - k < kChainMaxSteps && fusable(j + 1) &&
+             p.steps[j + 1].a == n + j && p.steps[j + 1].phase == p.steps[k].phase &&
+             build_chain(p, lay, sbits, k, j + 1, cand)) {
+        g = cand;
+        ++j;
+      }
+      if (j > k) {
+        for (int q = k; q <= j; ++q) p.steps[q].chain = (int32_t)p.chains.size();
+        p.chains.push_back(g);
+      }
+      k = j + 1;
+    }
+  }
 
-  // arena
+  // schedule: phase 0, then phase 1; inside a phase a topological order that
+  // takes every ready small step before the next ready large one (path order
+  // among equals), so small steps form long segments
+  std::vector<int32_t> consumer(nn_nodes, -1);
+  for (int k = 0; k < nsteps; ++k) {
+    consumer[p.steps[k].a] = k;
+    consumer[p.steps[k].b] = k;
+  }
+  p.sched.clear();
+  for (int ph = 0; ph < 2; ++ph) {
+    std::vector<int32_t> pending(nsteps, 0);
+    std::vector<int32_t> rs, rb;   // ready small / large, kept sorted descending (pop back)
+    for (int k = 0; k < nsteps; ++k) {
+      if (p.steps[k].phase != ph) continue;
+      for (int x : {p.steps[k].a, p.steps[k].b})
+        if (x >= n && p.steps[x - n].phase == ph) pending[k]++;
+      if (pending[k] == 0) (p.steps[k].small ? rs : rb).push_back(k);
+    }
+    auto desc = [](std::vector<int32_t>& v) { std::sort(v.begin(), v.end(), std::greater<int32_t>()); };
+    desc(rs);
+    desc(rb);
+    while (!rs.empty() || !rb.empty()) {
+      int k;
+      if (!rs.empty()) { k = rs.back(); rs.pop_back(); } else { k = rb.back(); rb.pop_back(); }
+      p.sched.push_back(k);
+      int c = consumer[n + k];
+      if (c >= 0 && p.steps[c].phase == ph && --pending[c] == 0) {
+        (p.steps[c].small ? rs : rb).push_back(c);
+        desc(rs);
+        desc(rb);
+      }
+    }
+    if (ph == 0) p.n_phase0 = (int32_t)p.sched.size();
+  }
+  // segments: runs of >= 2 consecutive small steps of one phase
+  p.segments.clear();
+  p.persist_bytes = 0;
+  for (size_t i = 0; i < p.sched.size();) {
+    const StepDesc& S = p.steps[p.sched[i]];
+    size_t j = i;
+    while (j < p.sched.size() && p.steps[p.sched[j]].small && p.steps[p.sched[j]].phase == S.phase) ++j;
+    if (j - i >= 2) {
+      Segment g{(int32_t)i, (int32_t)j, 0, S.phase};
+      for (size_t q = i; q < j; ++q) {
+        const StepDesc& T = p.steps[p.sched[q]];
+        int ob = (int)(T.bA.size() + T.mA.size() + T.nB.size());
+        g.n_items += (int32_t)(((int64_t)1 << ob) + 255) / 256;
+      }
+      p.segments.push_back(g);
+      i = j;
+    } else {
+      i = std::max(j, i + 1);
+    }
+  }
+
+  // arena.  Steps of one persistent segment run concurrently, so buffers
+  // freed by a segment step are returned only when the whole segment is done.
+  std::vector<int32_t> seg_last(p.sched.size(), -1);   // position -> end of its segment - 1
+  for (const Segment& g : p.segments)
+    for (int q = g.begin; q < g.end; ++q) seg_last[q] = g.end - 1;
   Arena ar;
   p.bytes_no_deletion = 0;
   p.scratch_bytes = 0;
+  std::vector<std::pair<int64_t, int64_t>> deferred;
   for (size_t pos = 0; pos < p.sched.size(); ++pos) {
-    StepDesc& S = p.steps[p.sched[pos]];
+    const int sk = p.sched[pos];
+    StepDesc& S = p.steps[sk];
+    // a chain runs at the position of its last step: one result, and the
+    // inputs of all its steps released there
+    if (S.chain >= 0 && p.chains[S.chain].last != sk) {
+      S.c_off = -1;
+      continue;
+    }
     S.c_off = ar.alloc(S.c_bytes);
     p.bytes_no_deletion += align_up(S.c_bytes, 256);
     p.scratch_bytes = std::max(p.scratch_bytes, S.scratch_bytes);
-    for (int x : {S.a, S.b}) {
+    std::vector<int32_t> ins;
+    if (S.chain >= 0) {
+      const ChainGroup& g = p.chains[S.chain];
+      ins.push_back(p.steps[g.first].a);
+      for (int q = g.first; q <= g.last; ++q) ins.push_back(p.steps[q].b);
+    } else {
+      ins = {S.a, S.b};
+    }
+    for (int x : ins) {
       if (x < n) continue;
       const StepDesc& X = p.steps[x - n];
-      if (X.phase == S.phase) ar.release(X.c_off, X.c_bytes);
+      if (X.phase != S.phase) continue;
+      if (seg_last[pos] >= 0) deferred.push_back({X.c_off, X.c_bytes});
+      else ar.release(X.c_off, X.c_bytes);
+    }
+    if (seg_last[pos] == (int32_t)pos) {
+      for (auto& d : deferred) ar.release(d.first, d.second);
+      deferred.clear();
     }
   }
   p.arena_bytes = ar.top;
@@ -324,7 +598,29 @@ static void schedule(Plan& p) {
   p.n_launches = launches0 + (int32_t)iters * (launches1 + 1) + 1;
   int64_t ctrl = align_up((int64_t)4 << p.resident_bits, 256);
   p.ctrl_bytes = ctrl;
-  p.workspace_bytes = align_up(p.arena_bytes, 256) + align_up(p.scratch_bytes, 256) + ctrl;
+  // persistent segments: one copy per (segment, execution) of descriptors,
+  // item tables and counters
+  int64_t pb = 0;
+  for (const Segment& g : p.segments) {
+    int64_t len = g.end - g.begin;
+    int64_t one = align_up(len * kSmallStepBytes, 256) + align_up((int64_t)4 * g.n_items, 256) +
+                  align_up((int64_t)4 * kCtrStride * (len + 2), 256);
+    pb += one * (g.phase ? (int64_t)iters : 1);
+  }
+  p.persist_bytes = pb;
+  p.workspace_bytes = align_up(p.arena_bytes, 256) + align_up(p.scratch_bytes, 256) + ctrl + pb;
+  // launches: persistent segments replace their steps' launches (plus a fill)
+  for (const Segment& g : p.segments) {
+    int32_t saved = 0;
+    for (int q = g.begin; q < g.end; ++q) saved += p.steps[p.sched[q]].kind == KIND_SPLITK ? 2 : 1;
+    int32_t d = saved - 2;
+    p.n_launches -= g.phase ? (int32_t)iters * d : d;
+  }
+  // chains: one launch for all their steps
+  for (const ChainGroup& g : p.chains) {
+    int32_t d = g.last - g.first;
+    p.n_launches -= g.phase ? (int32_t)iters * d : d;
+  }
 
   // backward: all forward results kept (checkpointing everything), gradient
   // buffers of intermediates allocated when produced and freed after use.
@@ -552,8 +848,10 @@ std::string build_plan(Plan& p, int32_t n_tensors, const int32_t* ranks,
     return false;
   };
   while (too_big(p)) {
-    // move the sliced index whose outer looping costs the least work
+    // move the sliced index whose outer looping makes the plan fit, else
+    // costs the least work (then the smallest peak)
     int best = -1;
+    bool best_fits = false;
     double best_cost = 0;
     int64_t best_peak = 0;
     std::vector<int32_t> base = p.outer_idx;
@@ -562,9 +860,13 @@ std::string build_plan(Plan& p, int32_t n_tensors, const int32_t* ranks,
       p.outer_idx = base;
       p.outer_idx.push_back(e);
       schedule(p);
-      double cost = p.cmac_exec;
-      if (best < 0 || cost < best_cost || (cost == best_cost && p.arena_bytes < best_peak)) {
+      const bool fits = !too_big(p);
+      const double cost = p.cmac_exec;
+      if (best < 0 || (fits && !best_fits) ||
+          (fits == best_fits &&
+           (cost < best_cost || (cost == best_cost && p.arena_bytes < best_peak)))) {
         best = e;
+        best_fits = fits;
         best_cost = cost;
         best_peak = p.arena_bytes;
       }

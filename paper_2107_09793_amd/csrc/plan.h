@@ -32,6 +32,49 @@ struct StepDesc {
   int64_t scratch_bytes;  // split-k partials
   int32_t splitk_chunks;
   int32_t tile;           // GEMM tile configuration
+  bool small = false;     // runs inside a persistent segment
+  int32_t chain = -1;     // chain group this step belongs to
+};
+
+// A run of consecutive small steps in the schedule executed by one launch.
+struct Segment {
+  int32_t begin, end;     // positions in Plan::sched
+  int32_t n_items;        // work items (chunks of 256 outputs)
+  int32_t phase;
+};
+
+constexpr int kSmallClassBits = 24;     // per class, to fit the device descriptor
+constexpr int64_t kSmallStepBytes = 272; // sizeof the device descriptor
+constexpr int64_t kCtrStride = 32;       // int32 slots between completion counters
+
+// A chain: consecutive stream steps (path order) where each step's large
+// operand is the previous step's result and its small operand is read whole
+// per tile.  One launch runs the chain over tiles of the running tensor: a
+// workgroup loads the tile bits of the chain input (the bits the chain
+// contracts, plus low-stride bits for coalescing) into LDS, applies every step
+// there, and writes the tile bits of the chain output.  Intermediate results
+// of the chain never reach HBM.
+constexpr int kChainMaxSteps = 8;
+constexpr int kChainTileBits = 12;   // LDS tile: 2^12 complex64 per buffer
+constexpr int kChainPassive = 40;    // bits enumerating tiles
+constexpr int kChainBElems = 1024;   // small operands staged in LDS, all steps
+
+struct ChainStepDesc {
+  int32_t step;                      // step index
+  int32_t nrow;                      // live tile bits that are not summed
+  std::vector<int8_t> kslot, nslot, rslot;   // LDS slots of summed / new / row bits
+  std::vector<int8_t> kB, nB;        // small-operand strides of summed / new bits
+  std::vector<int8_t> bB, bpas;      // batch bits: small-operand stride, passive-bit index
+};
+
+struct ChainGroup {
+  int32_t first = 0, last = 0;       // step indices (path order), inclusive
+  int32_t phase = 0;
+  int32_t tile_bits = 0;             // slots used (LDS buffer = 2^tile_bits)
+  std::vector<int8_t> in_slot, in_log2;    // input tile bits, input-stride order
+  std::vector<int8_t> out_slot, out_log2;  // output tile bits, output-stride order
+  std::vector<int8_t> pas_in, pas_out;     // passive bits: input / output strides
+  std::vector<ChainStepDesc> st;
 };
 
 struct LeafDesc {
@@ -67,6 +110,9 @@ struct Plan {
   std::vector<StepDesc> steps;               // path order
   std::vector<int32_t> sched;                // step indices, execution order
   int32_t n_phase0 = 0;                      // sched[0 .. n_phase0) run once
+  std::vector<Segment> segments;             // persistent launches
+  std::vector<ChainGroup> chains;            // fused chains of stream steps
+  int64_t persist_bytes = 0;                 // control region for one tn_contract
 
   // outer / resident split (whole sliced indices)
   std::vector<int32_t> outer_idx, resident_idx;   // sliced index ids

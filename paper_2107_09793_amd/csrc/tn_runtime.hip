@@ -16,12 +16,18 @@
 
 #include "../../include/tn.h"
 #include "kernels_basic.h"
+#include "kernels_chain.h"
 #include "kernels_gemm.h"
+#include "kernels_persist.h"
 #include "plan.h"
 
 struct tn_plan_s {
   tn::Plan p;
 };
+
+static_assert(sizeof(tnk::SmallStep) == tn::kSmallStepBytes, "descriptor size");
+static_assert(tnk::kSmallBits == tn::kSmallClassBits, "descriptor bits");
+static_assert(tnk::kCtrStride == tn::kCtrStride, "counter spacing");
 
 namespace {
 
@@ -71,8 +77,13 @@ tnk::StepArgs make_args(const tn::StepDesc& S) {
 
 template <int NK, int NN>
 void launch_stream_nn(const tnk::StreamArgs& a, uint64_t rows, hipStream_t st) {
-  hipLaunchKernelGGL((tnk::k_stream<NK, NN>), dim3(grid_for(rows, 1u << 16)), dim3(tnk::kBlock),
-                     0, st, a);
+  const bool shb = a.nbB == 0 || a.nrow - a.nbB >= 8;
+  if (shb)
+    hipLaunchKernelGGL((tnk::k_stream<NK, NN, true>), dim3(grid_for(rows, 1u << 16)),
+                       dim3(tnk::kBlock), 0, st, a);
+  else
+    hipLaunchKernelGGL((tnk::k_stream<NK, NN, false>), dim3(grid_for(rows, 1u << 16)),
+                       dim3(tnk::kBlock), 0, st, a);
 }
 
 template <int NK>
@@ -154,6 +165,11 @@ int64_t max_tile_offset(int L1, const int8_t* s1, int n1, int L2, const int8_t* 
   return m;
 }
 
+template <auto Kernel>
+void launch_tiles(uint64_t ntiles, const tnk::GemmArgs& g, hipStream_t st) {
+  hipLaunchKernelGGL(Kernel, dim3((unsigned)ntiles), dim3(256), 0, st, g);
+}
+
 template <int WVM, int WVN, int WM, int WN, int LK>
 tn_status launch_gemm_cfg(const tnk::StepArgs& a, int32_t precision, hipStream_t st) {
   constexpr int MT = WVM * WM * 32, NT = WVN * WN * 16;
@@ -171,17 +187,12 @@ tn_status launch_gemm_cfg(const tnk::StepArgs& a, int32_t precision, hipStream_t
   g.xcd_remap = ntiles >= 64 ? 1 : 0;
   const bool small = max_tile_offset(LM, a.sA_m, a.nm, lk, a.sA_k, a.nk) < (1ll << 31) &&
                      max_tile_offset(LN, a.sB_n, a.nn, lk, a.sB_k, a.nk) < (1ll << 31);
-  dim3 grid((unsigned)ntiles), blk(256);
   if (precision == tn::PREC_SPLIT_BF16) {
-    if (small)
-      hipLaunchKernelGGL((tnk::k_gemm_sb16<WVM, WVN, WM, WN, int32_t>), grid, blk, 0, st, g);
-    else
-      hipLaunchKernelGGL((tnk::k_gemm_sb16<WVM, WVN, WM, WN, int64_t>), grid, blk, 0, st, g);
+    if (small) launch_tiles<tnk::k_gemm_sb16<WVM, WVN, WM, WN, int32_t>>(ntiles, g, st);
+    else launch_tiles<tnk::k_gemm_sb16<WVM, WVN, WM, WN, int64_t>>(ntiles, g, st);
   } else {
-    if (small)
-      hipLaunchKernelGGL((tnk::k_gemm_c64<WVM, WVN, WM, WN, LK, int32_t>), grid, blk, 0, st, g);
-    else
-      hipLaunchKernelGGL((tnk::k_gemm_c64<WVM, WVN, WM, WN, LK, int64_t>), grid, blk, 0, st, g);
+    if (small) launch_tiles<tnk::k_gemm_c64<WVM, WVN, WM, WN, LK, int32_t>>(ntiles, g, st);
+    else launch_tiles<tnk::k_gemm_c64<WVM, WVN, WM, WN, LK, int64_t>>(ntiles, g, st);
   }
   return TN_OK;
 }
@@ -279,8 +290,167 @@ tn_status run_step(const Ctx& c, int k, uint64_t outer_val, Probe* probe = nullp
   return s;
 }
 
+// One fused chain (all its steps, one launch).
+tn_status run_chain(const Ctx& c, const tn::ChainGroup& g, uint64_t outer_val,
+                    Probe* probe = nullptr) {
+  const tn::Plan& p = c.p;
+  static_assert(sizeof(tnk::ChainArgs) % 4 == 0, "argument copy in 32-bit words");
+  static_assert(tnk::kChainSteps == tn::kChainMaxSteps && tnk::kChainTile == tn::kChainTileBits &&
+                    tnk::kChainPas == tn::kChainPassive && tnk::kChainB == tn::kChainBElems,
+                "chain limits agree");
+  tnk::ChainArgs a;
+  memset(&a, 0, sizeof a);
+  const tn::StepDesc& F = p.steps[g.first];
+  const tn::StepDesc& L = p.steps[g.last];
+  a.X = node_ptr(c, F.a, outer_val);
+  a.Y = reinterpret_cast<float2*>(c.ws + L.c_off);
+  a.nsteps = (int32_t)g.st.size();
+  a.tin = (int32_t)g.in_slot.size();
+  a.tout = (int32_t)g.out_slot.size();
+  a.npas = (int32_t)g.pas_in.size();
+  for (size_t i = 0; i < g.in_slot.size(); ++i) {
+    a.in_slot[i] = g.in_slot[i];
+    a.in_log2[i] = g.in_log2[i];
+  }
+  for (size_t i = 0; i < g.out_slot.size(); ++i) {
+    a.out_slot[i] = g.out_slot[i];
+    a.out_log2[i] = g.out_log2[i];
+  }
+  for (size_t i = 0; i < g.pas_in.size(); ++i) {
+    a.pas_in[i] = g.pas_in[i];
+    a.pas_out[i] = g.pas_out[i];
+  }
+  int total = 0;
+  for (size_t q = 0; q < g.st.size(); ++q) {
+    const tn::ChainStepDesc& d = g.st[q];
+    tnk::ChainStepArgs& t = a.st[q];
+    t.B = node_ptr(c, p.steps[d.step].b, outer_val);
+    t.nk = (int8_t)d.kslot.size();
+    t.nn = (int8_t)d.nslot.size();
+    t.nrow = (int8_t)d.nrow;
+    t.nbb = (int8_t)d.bB.size();
+    for (size_t j = 0; j < d.kslot.size(); ++j) {
+      t.kslot[j] = d.kslot[j];
+      t.kB[j] = d.kB[j];
+    }
+    for (size_t j = 0; j < d.nslot.size(); ++j) {
+      t.nslot[j] = d.nslot[j];
+      t.nB[j] = d.nB[j];
+    }
+    for (size_t j = 0; j < d.rslot.size(); ++j) t.rslot[j] = d.rslot[j];
+    for (size_t j = 0; j < d.bB.size(); ++j) {
+      t.bB[j] = d.bB[j];
+      t.bpas[j] = d.bpas[j];
+    }
+    if (!d.bB.empty()) a.b_per_tile = 1;
+    total += 1 << (t.nk + t.nn);
+  }
+  a.b_total = total;
+  if (total > tnk::kChainB || g.tile_bits > tnk::kChainTile)
+    return fail(TN_E_INVALID, "chain exceeds its on-chip limits");
+  const uint64_t n_tiles = 1ull << a.npas;
+  const unsigned grid = (unsigned)std::min<uint64_t>(n_tiles, 1u << 16);
+  bool timed = false;
+  if (probe && !probe->done)
+    for (int k = g.first; k <= g.last; ++k) timed |= probe->step == k;
+  if (timed) TN_HIP_CHECK(hipEventRecord(probe->start, c.st));
+  if (g.tile_bits <= 10)
+    hipLaunchKernelGGL(tnk::k_chain<10>, dim3(grid), dim3(256), 0, c.st, a);
+  else if (g.tile_bits == 11)
+    hipLaunchKernelGGL(tnk::k_chain<11>, dim3(grid), dim3(256), 0, c.st, a);
+  else
+    hipLaunchKernelGGL(tnk::k_chain<12>, dim3(grid), dim3(256), 0, c.st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(TN_E_HIP, std::string("chain launch: ") + hipGetErrorString(e));
+  if (timed) {
+    TN_HIP_CHECK(hipEventRecord(probe->stop, c.st));
+    probe->done = true;
+  }
+  return TN_OK;
+}
 
 }  // namespace
+
+// Control region of the persistent segments: for every (segment, execution)
+// the device descriptors, the item -> step table and zeroed counters, built on
+// the host and copied with one transfer at the start of tn_contract.
+struct SegLayout {
+  int64_t off_desc, off_items, off_ctr;
+};
+
+static int64_t al256(int64_t x) { return (x + 255) / 256 * 256; }
+
+static void build_persist_blob(const Ctx& c, std::vector<char>& blob,
+                               std::vector<std::vector<SegLayout>>& lay) {
+  const tn::Plan& p = c.p;
+  const int n = p.n_tensors;
+  const uint64_t n_it = 1ull << p.outer_bits;
+  blob.assign((size_t)p.persist_bytes, 0);
+  lay.assign(p.segments.size(), {});
+  std::vector<int32_t> pos_of(p.steps.size(), -1);
+  for (size_t q = 0; q < p.sched.size(); ++q) pos_of[p.sched[q]] = (int32_t)q;
+  int64_t off = 0;
+  for (size_t gi = 0; gi < p.segments.size(); ++gi) {
+    const tn::Segment& g = p.segments[gi];
+    const int len = g.end - g.begin;
+    const uint64_t execs = g.phase ? n_it : 1;
+    for (uint64_t e = 0; e < execs; ++e) {
+      SegLayout L;
+      L.off_desc = off;
+      L.off_items = L.off_desc + al256((int64_t)len * tn::kSmallStepBytes);
+      L.off_ctr = L.off_items + al256((int64_t)4 * g.n_items);
+      off = L.off_ctr + al256((int64_t)4 * tnk::kCtrStride * (len + 2));
+      tnk::SmallStep* d = reinterpret_cast<tnk::SmallStep*>(blob.data() + L.off_desc);
+      int32_t* items = reinterpret_cast<int32_t*>(blob.data() + L.off_items);
+      int32_t item = 0;
+      for (int i = 0; i < len; ++i) {
+        const tn::StepDesc& S = p.steps[p.sched[g.begin + i]];
+        tnk::SmallStep& D = d[i];
+        memset(&D, 0, sizeof D);
+        D.A = node_ptr(c, S.a, e);
+        D.B = node_ptr(c, S.b, e);
+        D.C = reinterpret_cast<float2*>(c.ws + S.c_off);
+        D.nb = (int32_t)S.bA.size();
+        D.nm = (int32_t)S.mA.size();
+        D.nn = (int32_t)S.nB.size();
+        D.nk = (int32_t)S.kA.size();
+        copy_bits(D.sA_b, S.bA); copy_bits(D.sB_b, S.bB); copy_bits(D.sC_b, S.bC);
+        copy_bits(D.sA_m, S.mA); copy_bits(D.sC_m, S.mC);
+        copy_bits(D.sB_n, S.nB); copy_bits(D.sC_n, S.nC);
+        copy_bits(D.sA_k, S.kA); copy_bits(D.sB_k, S.kB);
+        const int64_t outs = (int64_t)1 << (D.nb + D.nm + D.nn);
+        D.n_items = (int32_t)((outs + 255) / 256);
+        D.item0 = item;
+        for (int32_t q = 0; q < D.n_items; ++q) items[item + q] = i;
+        item += D.n_items;
+        int32_t dep[2] = {-1, -1};
+        int nd = 0;
+        for (int x : {S.a, S.b}) {
+          if (x < n) continue;
+          int32_t ps = pos_of[x - n];
+          if (ps >= g.begin && ps < g.end) dep[nd++] = ps - g.begin;
+        }
+        D.dep0 = dep[0];
+        D.dep1 = dep[1];
+      }
+      lay[gi].push_back(L);
+    }
+  }
+}
+
+static tn_status launch_segment(const Ctx& c, const tn::Segment& g, const SegLayout& L,
+                                char* pbase) {
+  const int len = g.end - g.begin;
+  int32_t* ctr = reinterpret_cast<int32_t*>(pbase + L.off_ctr);
+  unsigned grid = (unsigned)(g.n_items < 2048 ? g.n_items : 2048);
+  hipLaunchKernelGGL(tnk::k_persistent, dim3(grid), dim3(256), 0, c.st,
+                     reinterpret_cast<const tnk::SmallStep*>(pbase + L.off_desc),
+                     reinterpret_cast<const int32_t*>(pbase + L.off_items), g.n_items, ctr,
+                     ctr + tnk::kCtrStride * (len + 1));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(TN_E_HIP, std::string("persistent launch: ") + hipGetErrorString(e));
+  return TN_OK;
+}
 
 static tn_status contract_impl(tn_plan_t plan, const void* const* leaves,
                                const int64_t* slice_ids, int64_t n_slice_ids, int32_t out_mode,
@@ -354,6 +524,8 @@ tn_status tn_plan_query(tn_plan_t plan, tn_plan_info* out) {
   copy_bits(out->root_res_log2, p.root_res_log2);
   for (int j = 0; j < p.resident_bits; ++j) out->res_slicebit[j] = (int8_t)p.res_slicebit[j];
   for (int j = 0; j < p.outer_bits; ++j) out->outer_slicebit[j] = (int8_t)p.outer_slicebit[j];
+  out->n_chains = (int32_t)p.chains.size();
+  out->n_segments = (int32_t)p.segments.size();
   return TN_OK;
 }
 
@@ -386,6 +558,46 @@ tn_status tn_plan_step(tn_plan_t plan, int32_t step, tn_step_info* out) {
   copy_bits(out->sB_k, S.kB);
   out->c_offset = S.c_off;
   out->c_bytes = S.c_bytes;
+  out->chain = S.chain;
+  return TN_OK;
+}
+
+tn_status tn_plan_chain(tn_plan_t plan, int32_t i, tn_chain_info* out) {
+  if (!plan || !out) return fail(TN_E_INVALID, "NULL argument");
+  const tn::Plan& p = plan->p;
+  if (i < 0 || i >= (int32_t)p.chains.size()) return fail(TN_E_INVALID, "chain index out of range");
+  const tn::ChainGroup& g = p.chains[i];
+  memset(out, 0, sizeof *out);
+  out->first = g.first;
+  out->last = g.last;
+  out->phase = g.phase;
+  out->tile_bits = g.tile_bits;
+  out->n_in = (int32_t)g.in_slot.size();
+  out->n_out = (int32_t)g.out_slot.size();
+  out->n_passive = (int32_t)g.pas_in.size();
+  out->n_steps = (int32_t)g.st.size();
+  copy_bits(out->in_slot, g.in_slot);
+  copy_bits(out->in_log2, g.in_log2);
+  copy_bits(out->out_slot, g.out_slot);
+  copy_bits(out->out_log2, g.out_log2);
+  copy_bits(out->pas_in, g.pas_in);
+  copy_bits(out->pas_out, g.pas_out);
+  for (size_t q = 0; q < g.st.size(); ++q) {
+    const tn::ChainStepDesc& d = g.st[q];
+    tn_chain_step_info& t = out->st[q];
+    t.step = d.step;
+    t.nrow = d.nrow;
+    t.nk = (int32_t)d.kslot.size();
+    t.nn = (int32_t)d.nslot.size();
+    t.nbb = (int32_t)d.bB.size();
+    copy_bits(t.kslot, d.kslot);
+    copy_bits(t.nslot, d.nslot);
+    copy_bits(t.kB, d.kB);
+    copy_bits(t.nB, d.nB);
+    copy_bits(t.rslot, d.rslot);
+    copy_bits(t.bB, d.bB);
+    copy_bits(t.bpas, d.bpas);
+  }
   return TN_OK;
 }
 
@@ -450,17 +662,62 @@ static tn_status contract_impl(tn_plan_t plan, const void* const* leaves, const 
                        n_out);
     TN_HIP_CHECK(hipGetLastError());
   }
+  // persistent segments: descriptors for every execution, one upload
+  std::vector<std::vector<SegLayout>> lay;
+  std::vector<int32_t> seg_at(p.sched.size(), -1);
+  char* pbase = c.ws + al256(p.arena_bytes) + al256(p.scratch_bytes) + p.ctrl_bytes;
+  if (!p.segments.empty()) {
+    std::vector<char> blob;
+    build_persist_blob(c, blob, lay);
+    // pageable source: the copy is staged before hipMemcpyAsync returns
+    TN_HIP_CHECK(hipMemcpyAsync(pbase, blob.data(), blob.size(), hipMemcpyHostToDevice, st));
+    for (size_t gi = 0; gi < p.segments.size(); ++gi) seg_at[p.segments[gi].begin] = (int32_t)gi;
+  }
+  auto run_range = [&](size_t from, size_t to, uint64_t it) -> tn_status {
+    for (size_t i = from; i < to;) {
+      const int32_t gi = seg_at[i];
+      if (gi >= 0) {
+        const tn::Segment& g = p.segments[gi];
+        bool timed = false;
+        if (probe && !probe->done)
+          for (int q = g.begin; q < g.end; ++q) timed |= p.sched[q] == probe->step;
+        if (timed) TN_HIP_CHECK(hipEventRecord(probe->start, st));
+        tn_status s = launch_segment(c, g, lay[gi][g.phase ? it : 0], pbase);
+        if (s != TN_OK) return s;
+        if (timed) {
+          TN_HIP_CHECK(hipEventRecord(probe->stop, st));
+          probe->done = true;
+        }
+        i = g.end;
+        continue;
+      }
+      const tn::StepDesc& S = p.steps[p.sched[i]];
+      if (S.chain >= 0) {   // a chain runs at the position of its last step
+        const tn::ChainGroup& g = p.chains[S.chain];
+        if (g.last == p.sched[i]) {
+          tn_status s = run_chain(c, g, it, probe);
+          if (s != TN_OK) return s;
+        }
+        ++i;
+        continue;
+      }
+      tn_status s = run_step(c, p.sched[i], it, probe);
+      if (s != TN_OK) return s;
+      ++i;
+    }
+    return TN_OK;
+  };
   // shared work: steps that depend on no outer index, once
-  for (int i = 0; i < p.n_phase0; ++i) {
-    tn_status s = run_step(c, p.sched[i], 0, probe);
+  {
+    tn_status s = run_range(0, p.n_phase0, 0);
     if (s != TN_OK) return s;
   }
   const uint64_t n_it = 1ull << p.outer_bits;
   const int root_step = p.n_tensors - 2;
   for (uint64_t it = 0; it < n_it; ++it) {
     if (!all && sel.find(it) == sel.end()) continue;
-    for (size_t i = p.n_phase0; i < p.sched.size(); ++i) {
-      tn_status s = run_step(c, p.sched[i], it, probe);
+    {
+      tn_status s = run_range(p.n_phase0, p.sched.size(), it);
       if (s != TN_OK) return s;
     }
     tnk::SumArgs sa;
@@ -618,18 +875,60 @@ tn_status tn_permute(const void* in, void* out, int32_t nbits, const int8_t* in_
   }
   uint64_t full = nbits == 64 ? ~0ull : ((1ull << nbits) - 1);
   if (seen_in != full || seen_out != full) return fail(TN_E_INVALID, "strides are not a permutation");
-  tnk::PermArgs a;
-  memset(&a, 0, sizeof a);
-  a.in = static_cast<const float2*>(in);
-  a.out = static_cast<float2*>(out);
-  a.nbits = nbits;
-  for (int j = 0; j < nbits; ++j) {
-    a.sin[j] = in_log2[j];
-    a.sout[j] = out_log2[j];
-  }
   hipStream_t st = static_cast<hipStream_t>(stream);
-  hipLaunchKernelGGL(tnk::k_permute_plain, dim3(grid_for(1ull << nbits)), dim3(tnk::kBlock), 0,
-                     st, a);
+  if (nbits < 10) {   // at most 512 elements: one element per thread
+    tnk::PermArgs a;
+    memset(&a, 0, sizeof a);
+    a.in = static_cast<const float2*>(in);
+    a.out = static_cast<float2*>(out);
+    a.nbits = nbits;
+    for (int j = 0; j < nbits; ++j) {
+      a.sin[j] = in_log2[j];
+      a.sout[j] = out_log2[j];
+    }
+    hipLaunchKernelGGL(tnk::k_permute_plain, dim3(grid_for(1ull << nbits)), dim3(tnk::kBlock),
+                       0, st, a);
+  } else {
+    tnk::PermTileArgs a;
+    memset(&a, 0, sizeof a);
+    a.in = static_cast<const float2*>(in);
+    a.out = static_cast<float2*>(out);
+    const int tb = nbits >= 12 ? 12 : 10, half = tb / 2;
+    // tile bits: every bit with an input or output stride below 2^half, then
+    // further bits by smallest stride until the tile has tb bits
+    std::vector<int> tile, rest;
+    for (int j = 0; j < nbits; ++j)
+      if (in_log2[j] < half || out_log2[j] < half) tile.push_back(j);
+    std::vector<int> others;
+    for (int j = 0; j < nbits; ++j)
+      if (!(in_log2[j] < half || out_log2[j] < half)) others.push_back(j);
+    std::sort(others.begin(), others.end(), [&](int x, int y) {
+      return std::min(in_log2[x], out_log2[x]) < std::min(in_log2[y], out_log2[y]);
+    });
+    for (int j : others) ((int)tile.size() < tb ? tile : rest).push_back(j);
+    std::vector<int> rd = tile, wr = tile;
+    std::sort(rd.begin(), rd.end(), [&](int x, int y) { return in_log2[x] < in_log2[y]; });
+    std::sort(wr.begin(), wr.end(), [&](int x, int y) { return out_log2[x] < out_log2[y]; });
+    std::sort(rest.begin(), rest.end(), [&](int x, int y) { return in_log2[x] < in_log2[y]; });
+    a.tbits = tb;
+    a.rbits = (int)rest.size();
+    a.half = half;
+    for (int p = 0; p < tb; ++p) {
+      a.rin[p] = in_log2[rd[p]];
+      a.wout[p] = out_log2[wr[p]];
+      a.wpos[p] = (int8_t)(std::find(rd.begin(), rd.end(), wr[p]) - rd.begin());
+    }
+    for (int q = 0; q < a.rbits; ++q) {
+      a.tin[q] = in_log2[rest[q]];
+      a.tout[q] = out_log2[rest[q]];
+    }
+    const uint64_t n_tiles = 1ull << a.rbits;
+    const unsigned grid = (unsigned)std::min<uint64_t>(n_tiles, 1u << 16);
+    if (tb == 12)
+      hipLaunchKernelGGL(tnk::k_permute_tile<12>, dim3(grid), dim3(tnk::kBlock), 0, st, a);
+    else
+      hipLaunchKernelGGL(tnk::k_permute_tile<10>, dim3(grid), dim3(tnk::kBlock), 0, st, a);
+  }
   TN_HIP_CHECK(hipGetLastError());
   return TN_OK;
 }

@@ -1,0 +1,64 @@
+"""Fused chains of stream steps on the GPU against the same steps launched
+one by one: each output value is formed by the same complex FMAs in the same
+order either way, so results must agree bit for bit; both are also checked
+against the complex128 oracle (1e-5)."""
+
+import numpy as np
+import pytest
+
+from oracle import tn_oracle
+from tngen import circuits, network, path as tpath, slicing, workloads
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _batch_net(seed, rows, cols, depth, batch, n_slice):
+    circ = circuits.grid_rqc(rows, cols, depth, seed=seed)
+    b = circuits.random_bitstrings(circ.n, 2, batch, seed)
+    tn = network.relabel_compact(network.circuit_network(circ, batch=b))
+    p = tpath.greedy_path(tn.labels, tn.dims, tn.open)
+    sl = slicing.greedy_slices(slicing.TreeSets(tn.labels, tn.dims, tn.open, p), n_slice=n_slice)
+    return tn, p, sl
+
+
+@pytest.mark.parametrize("cfg", [(3, 4, 4, 12, 16, 2), (7, 4, 4, 14, 32, 2), (9, 4, 4, 10, 16, 3),
+                                 (3, 4, 5, 12, 16, 2)])
+def test_chain_bitwise_equals_per_step(cfg):
+    from paper_2107_09793_amd import Plan
+    dev = _dev()
+    tn, p, sl = _batch_net(*cfg)
+    leaves = [torch.from_numpy(t.astype(np.complex64)).to(dev) for t in tn.tensors]
+    fused = Plan.from_network(tn, p, sl, persistent=False)
+    plain = Plan.from_network(tn, p, sl, persistent=False, chains=False)
+    assert fused.info()["n_chains"] > 0
+    a = fused.contract(leaves, per_slice=True).cpu().numpy()
+    b = plain.contract(leaves, per_slice=True).cpu().numpy()
+    assert np.array_equal(a, b)
+    ref = tn_oracle.contract(tn.tensors, tn.labels, tn.dims, tn.open, p, sl, per_slice=True)
+    ref = np.asarray(ref).reshape(a.shape)
+    rms = np.sqrt(np.mean(np.abs(ref) ** 2))
+    assert np.max(np.abs(a - ref)) <= 1e-5 * rms
+
+
+def test_chain_sliced_workload_bitwise():
+    """The 30-qubit 64-slice workload with its default plan (chains, no
+    persistent segments) against the same plan without chains."""
+    from paper_2107_09793_amd import Plan
+    dev = _dev()
+    w = workloads.build("sliced", seed=0)
+    leaves = [torch.from_numpy(np.ascontiguousarray(t, dtype=np.complex64)).to(dev)
+              for t in w.tn.tensors]
+    fused = Plan.from_network(w.tn, w.path, w.sliced)
+    plain = Plan.from_network(w.tn, w.path, w.sliced, chains=False)
+    a = fused.contract(leaves, per_slice=True).cpu().numpy()
+    del fused
+    torch.cuda.empty_cache()
+    b = plain.contract(leaves, per_slice=True).cpu().numpy()
+    assert np.array_equal(a, b)

@@ -41,23 +41,36 @@ def _plan(*a, **k):
     return Plan(*a, **k)
 
 
-def test_permute_bitwise():
+def _perm_ref(x, pin, pout):
+    """Definition: logical element i (bits i_j) is read at sum_j i_j 2^pin[j]
+    and written at sum_j i_j 2^pout[j]."""
+    idx = np.arange(x.size, dtype=np.int64)
+    src = np.zeros_like(idx)
+    dst = np.zeros_like(idx)
+    for j in range(len(pin)):
+        src |= ((idx >> j) & 1) << int(pin[j])
+        dst |= ((idx >> j) & 1) << int(pout[j])
+    ref = np.empty_like(x)
+    ref[dst] = x[src]
+    return ref
+
+
+@pytest.mark.parametrize("nbits", [1, 5, 9, 10, 11, 12, 13, 20, 26])
+def test_permute_bitwise(nbits):
+    """Plain kernel below 10 bits, LDS-tiled (10- and 12-bit tiles) above;
+    random permutations on both sides, plus identity and full reversal."""
     from paper_2107_09793_amd import permute
     dev = _dev()
-    rng = np.random.default_rng(0)
-    for nbits in (1, 5, 12, 20):
-        x = (rng.standard_normal(1 << nbits) + 1j * rng.standard_normal(1 << nbits)).astype(np.complex64)
-        pin = list(range(nbits))
-        pout = list(rng.permutation(nbits))
-        y = permute(torch.from_numpy(x).to(dev), pin, pout).cpu().numpy()
-        # numpy: element i (bits i_j) goes to sum_j i_j 2^pout[j]
-        idx = np.arange(1 << nbits)
-        dst = np.zeros_like(idx)
-        for j in range(nbits):
-            dst |= ((idx >> j) & 1) << pout[j]
-        ref = np.empty_like(x)
-        ref[dst] = x
-        assert np.array_equal(y, ref)
+    rng = np.random.default_rng(nbits)
+    x = (rng.standard_normal(1 << nbits) + 1j * rng.standard_normal(1 << nbits)).astype(np.complex64)
+    xd = torch.from_numpy(x).to(dev)
+    cases = [(list(range(nbits)), list(rng.permutation(nbits))),
+             (list(rng.permutation(nbits)), list(rng.permutation(nbits))),
+             (list(range(nbits)), list(range(nbits))),
+             (list(range(nbits)), list(reversed(range(nbits))))]
+    for pin, pout in cases:
+        y = permute(xd, pin, pout).cpu().numpy()
+        assert np.array_equal(y, _perm_ref(x, pin, pout)), (pin, pout)
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2])

@@ -161,25 +161,82 @@ def test_cpu_execution_of_plan_matches_oracle(case):
             assert np.allclose(per[:, r], parts[sid], rtol=1e-12, atol=1e-14)
 
 
-def test_liveness_never_overlaps_live_results():
-    tn, p = _small_net(seed=3, rows=4, cols=4, depth=8)
-    ts = slicing.TreeSets(tn.labels, tn.dims, tn.open, p)
-    sl = slicing.greedy_slices(ts, n_slice=3)
-    pl = Plan.from_network(tn, p, sl)
+def _batch_net(seed, rows, cols, depth, batch, n_slice):
+    circ = circuits.grid_rqc(rows, cols, depth, seed=seed)
+    b = circuits.random_bitstrings(circ.n, 2, batch, seed)
+    tn = network.relabel_compact(network.circuit_network(circ, batch=b))
+    p = tpath.greedy_path(tn.labels, tn.dims, tn.open)
+    sl = slicing.greedy_slices(slicing.TreeSets(tn.labels, tn.dims, tn.open, p), n_slice=n_slice)
+    return tn, p, sl
+
+
+@pytest.mark.parametrize("cfg", [(3, 4, 4, 12, 16, 2), (7, 4, 4, 14, 32, 2), (9, 4, 4, 10, 16, 3)])
+def test_cpu_execution_of_fused_chains_matches_oracle(cfg):
+    """Chains (consecutive stream steps run as one tiled pass) executed on the
+    CPU from their descriptors: tile loads through the input strides, LDS
+    slots, per-step small operands selected by passive batch bits, tile
+    stores through the output strides.  Every step outside a persistent
+    segment may join a chain, so small networks have chains with passive and
+    batch bits."""
+    tn, p, sl = _batch_net(*cfg)
+    pl = Plan.from_network(tn, p, sl, persistent=False)
+    info = pl.info()
+    chains = pl.chains()
+    assert info["n_chains"] == len(chains) > 0
+    assert any(ch["pas_in"] for ch in chains)
+    assert any(d["bB"] for ch in chains for d in ch["st"])
+    steps = pl.steps()
+    for ch in chains:
+        assert 2 <= len(ch["st"]) <= 8 and ch["tile_bits"] <= 12
+        for k in range(ch["first"], ch["last"]):
+            assert steps[k + 1]["a"] == pl.n_tensors + k and steps[k]["c_offset"] == -1
+        used = sum(2 ** (len(d["kslot"]) + len(d["nslot"])) for d in ch["st"])
+        assert used <= 1024
+    got, _ = execute(pl, tn.tensors)
+    ref = np.asarray(tn_oracle.contract(tn.tensors, tn.labels, tn.dims, tn.open, p, sl)).reshape(-1)
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-13 * np.max(np.abs(ref)))
+    unfused = Plan.from_network(tn, p, sl, persistent=False, chains=False)
+    assert unfused.info()["n_chains"] == 0
+    assert unfused.info()["n_launches"] - info["n_launches"] == sum(
+        ch["last"] - ch["first"] for ch in chains) * (1 << info["n_outer_bits"])
+
+
+def _live_ranges(pl):
+    """(produced, last used, start byte, end byte) of every stored result in
+    execution order; a chain produces its output and reads all its inputs at
+    the position of its last step."""
     steps = pl.steps()
     n = pl.n_tensors
+    chains = pl.chains()
     order = [k for k in range(n - 1) if steps[k]["phase"] == 0] + \
             [k for k in range(n - 1) if steps[k]["phase"] == 1]
+    order = [k for k in order if steps[k]["chain"] < 0 or chains[steps[k]["chain"]]["last"] == k]
     pos = {k: i for i, k in enumerate(order)}
     consumer = {}
     for k, s in enumerate(steps):
-        consumer[s["a"]] = k
-        consumer[s["b"]] = k
+        at = k if s["chain"] < 0 else chains[s["chain"]]["last"]
+        consumer[s["a"]] = at
+        consumer[s["b"]] = at
     live = []
     for k in order:
         s = steps[k]
         end = pos[consumer[n + k]] if (n + k) in consumer else len(order)
         live.append((pos[k], end, s["c_offset"], s["c_offset"] + s["c_bytes"]))
+    return live
+
+
+@pytest.mark.parametrize("fused", [False, True])
+def test_liveness_never_overlaps_live_results(fused):
+    if fused:
+        tn, p, sl = _batch_net(7, 4, 4, 14, 32, 2)
+        pl = Plan.from_network(tn, p, sl, persistent=False)
+        assert pl.info()["n_chains"] > 0
+    else:
+        tn, p = _small_net(seed=3, rows=4, cols=4, depth=8)
+        ts = slicing.TreeSets(tn.labels, tn.dims, tn.open, p)
+        sl = slicing.greedy_slices(ts, n_slice=3)
+        pl = Plan.from_network(tn, p, sl)
+    live = _live_ranges(pl)
     for i in range(len(live)):
         for j in range(i + 1, len(live)):
             a, b = live[i], live[j]
