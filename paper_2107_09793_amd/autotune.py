@@ -45,14 +45,17 @@ def time_step(plan, leaves, step, reps, torch):
 def tune(workload="sliced", seed=0, n_shapes=6, reps=3, precisions=("c64", "split_bf16"),
          out=None, log=print):
     import torch
-    from paper_2107_09793_amd.binding import Plan
+    from paper_2107_09793_amd.binding import Plan, default_workspace_limit
     from tngen import workloads
 
     w = workloads.build(workload, seed=seed)
     dev = torch.device("cuda:0")
     leaves = [torch.from_numpy(np.ascontiguousarray(t, dtype=np.complex64)).to(dev)
               for t in w.tn.tensors]
-    base = Plan.from_network(w.tn, w.path, w.sliced, tune=[])
+    # one workspace limit for every plan: the same outer split, so a step
+    # index has the same shape in every configuration
+    ws_limit = default_workspace_limit()
+    base = Plan.from_network(w.tn, w.path, w.sliced, tune=[], workspace_limit=ws_limit)
     steps = base.steps()
     gem = [k for k, s in enumerate(steps) if s["kind_name"] == "gemm"]
     gem.sort(key=lambda k: -steps[k]["cmac"])
@@ -70,7 +73,11 @@ def tune(workload="sliced", seed=0, n_shapes=6, reps=3, precisions=("c64", "spli
         times = {k: {} for k in chosen}
         for cfg in range(N_CONFIGS):
             pl = Plan.from_network(w.tn, w.path, w.sliced, precision=prec, gemm_config=cfg,
-                                   tune=[])
+                                   tune=[], workspace_limit=ws_limit)
+            for k in chosen:
+                got = pl.step(k)
+                assert (got["nb"], got["nm"], got["nn"], got["nk"]) == \
+                    (steps[k]["nb"], steps[k]["nm"], steps[k]["nn"], steps[k]["nk"])
             pl.contract(leaves, slice_ids=[0])
             torch.cuda.synchronize()
             for k in chosen:
@@ -82,7 +89,9 @@ def tune(workload="sliced", seed=0, n_shapes=6, reps=3, precisions=("c64", "spli
                                 nk=s["nk"], config=cfg, ms=ms, tflops=tf))
                 log(f"{prec:10s} step {k:4d} b{s['nb']} m{s['nm']} n{s['nn']} k{s['nk']} "
                     f"cfg {cfg} ({CONFIG_NAMES[cfg]}): {ms:9.3f} ms  {tf:7.2f} TFLOP/s")
+            pl.release_workspace()
             del pl
+            torch.cuda.empty_cache()
         for k in chosen:
             best = min(times[k], key=times[k].get)
             s = steps[k]
