@@ -62,8 +62,13 @@ def launch_units(plan, steps):
         f, l = mem[0], mem[-1]
         el = 2 ** (f["nb"] + f["nm"] + f["nk"]) + 2 ** (l["nb"] + l["nm"] + l["nn"])
         el += sum(2 ** (m["nb"] + m["nk"] + m["nn"]) for m in mem)
+        # steps the chain runs on the matrix cores (the plan's rule, see
+        # kernels_chain.h): 2^nk >= 4, 2^nn >= 8, at least 16 rows
+        on_mfma = [len(d["kslot"]) >= 2 and len(d["nslot"]) >= 3 and d["nrow"] >= 4
+                   and not plan.chain_valu for d in ch["st"]]
         units[ch["first"]] = dict(kind="chain", cmac=sum(m["cmac"] for m in mem), bytes=8.0 * el,
                                   phase=ch["phase"], steps=[d["step"] for d in ch["st"]],
+                                  cmac_mfma=sum(m["cmac"] for m, f in zip(mem, on_mfma) if f),
                                   shape=[dict(nb=m["nb"], nm=m["nm"], nn=m["nn"], nk=m["nk"])
                                          for m in mem])
     return units
@@ -93,17 +98,29 @@ def dominant_unit(plan, leaves, info, units, torch):
 def roofline(unit, avg_s, precision):
     """The unit's bound is the larger of its HBM time (algorithmic bytes at
     8 TB/s) and its compute time (MFMA for GEMM steps at the precision's
-    peak, counting the three products of split-BF16; FP32 vector FMA for the
-    others); achieved is measured in that bound's unit."""
+    peak, counting the three products of split-BF16; FP32 MFMA or FP32
+    vector FMA for chain steps, as the chain runs them; FP32 vector FMA for
+    the others); achieved is measured in that bound's unit against the peak
+    of the units doing most of the work."""
     kind = unit["kind"]
     if kind == "gemm":
         flops = 8.0 * unit["cmac"] * (3.0 if precision == "split_bf16" else 1.0)
         peak, cbound = PEAKS["mfma_" + precision], "mfma"
+        t_cmp = flops / (peak * 1e12)
+    elif kind == "chain":
+        # chain steps run on FP32 matrix cores or FP32 vector units
+        flops = 8.0 * unit["cmac"]
+        fm = 8.0 * unit["cmac_mfma"]
+        t_cmp = fm / (PEAKS["mfma_c64"] * 1e12) + (flops - fm) / (PEAKS["alu"] * 1e12)
+        if fm >= flops - fm:
+            peak, cbound = PEAKS["mfma_c64"], "mfma"
+        else:
+            peak, cbound = PEAKS["alu"], "alu"
     else:
         flops = 8.0 * unit["cmac"]
         peak, cbound = PEAKS["alu"], "alu"
+        t_cmp = flops / (peak * 1e12)
     t_mem = unit["bytes"] / (PEAKS["hbm"] * 1e9)
-    t_cmp = flops / (peak * 1e12)
     if t_mem >= t_cmp:
         ach = unit["bytes"] / avg_s / 1e9
         return dict(bound="hbm", achieved=ach, peak=PEAKS["hbm"], unit="GB/s",

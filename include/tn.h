@@ -64,6 +64,13 @@ typedef enum { TN_OUT_SUM = 0, TN_OUT_PER_SLICE = 1 } tn_out_mode;
 #define TN_FLAG_SIMPLE_KERNELS 2u /* force the plain per-element kernels (debug)     */
 #define TN_FLAG_NO_PERSISTENT 4u  /* no persistent segments (the default; kept so
                                      existing callers stay valid)                    */
+#define TN_FLAG_CHAIN_VALU 32u    /* chains compute every step on the vector units
+                                     (bitwise equal to per-step launches) instead of
+                                     the matrix cores for 2^nk >= 4, 2^nn >= 8       */
+#define TN_FLAG_CHAIN_STEPWISE 64u /* plan chains (and their layouts) but launch each
+                                     of their steps separately; with
+                                     TN_FLAG_CHAIN_VALU results are bitwise equal to
+                                     the fused launches                              */
 #define TN_FLAG_PERSISTENT 16u    /* experimental: run runs of small steps as one
                                      persistent launch each (workgroups claim work
                                      items and wait on completion counters)          */
@@ -153,8 +160,8 @@ typedef struct {
 typedef struct {
   int32_t step;               /* step index                                      */
   int32_t nrow, nk, nn, nbb;  /* row / summed / new bits, batch bits of B         */
-  int8_t kslot[4], nslot[4];  /* LDS slots of summed and new bits                 */
-  int8_t kB[4], nB[4];        /* B strides of summed and new bits                 */
+  int8_t kslot[8], nslot[8];  /* LDS slots of summed and new bits                 */
+  int8_t kB[8], nB[8];        /* B strides of summed and new bits                 */
   int8_t rslot[12];           /* LDS slots of the row bits                        */
   int8_t bB[12], bpas[12];    /* batch bits: B stride and tile-number bit         */
 } tn_chain_step_info;

@@ -57,7 +57,8 @@ def tune(workload="sliced", seed=0, n_shapes=6, reps=3, precisions=("c64", "spli
     ws_limit = default_workspace_limit()
     base = Plan.from_network(w.tn, w.path, w.sliced, tune=[], workspace_limit=ws_limit)
     steps = base.steps()
-    gem = [k for k, s in enumerate(steps) if s["kind_name"] == "gemm"]
+    # GEMM launches only: a step inside a fused chain runs on the chain kernel
+    gem = [k for k, s in enumerate(steps) if s["kind_name"] == "gemm" and s["chain"] < 0]
     gem.sort(key=lambda k: -steps[k]["cmac"])
     shapes, chosen = [], []
     for k in gem:

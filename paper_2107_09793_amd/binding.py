@@ -21,6 +21,8 @@ TN_FLAG_SIMPLE_KERNELS = 2
 TN_FLAG_NO_PERSISTENT = 4
 TN_FLAG_NO_CHAIN = 8
 TN_FLAG_PERSISTENT = 16
+TN_FLAG_CHAIN_VALU = 32
+TN_FLAG_CHAIN_STEPWISE = 64
 KIND_NAMES = {0: "simple", 1: "splitk", 2: "stream", 3: "gemm"}
 
 I8x48 = ctypes.c_int8 * 48
@@ -60,7 +62,7 @@ class StepInfo(ctypes.Structure):
 
 class ChainStepInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("step", "nrow", "nk", "nn", "nbb")] + \
-        [(n, ctypes.c_int8 * 4) for n in ("kslot", "nslot", "kB", "nB")] + \
+        [(n, ctypes.c_int8 * 8) for n in ("kslot", "nslot", "kB", "nB")] + \
         [(n, ctypes.c_int8 * 12) for n in ("rslot", "bB", "bpas")]
 
 
@@ -176,7 +178,8 @@ class Plan:
 
     def __init__(self, labels, dims, open_ids, path, sliced=(), precision="c64",
                  max_resident_bits=-1, workspace_limit="auto", no_reuse=False, simple=False,
-                 gemm_config=-1, tune="default", persistent=False, chains=True):
+                 gemm_config=-1, tune="default", persistent=False, chains=True,
+                 chain_mfma=True, chain_fused=True):
         n_index = (max(dims) + 1) if isinstance(dims, dict) else len(dims)
         dim_arr = [dims[i] for i in range(n_index)]
         ranks, r_p = _i32([len(l) for l in labels])
@@ -192,7 +195,9 @@ class Plan:
             else int(workspace_limit)
         opts.flags = (TN_FLAG_NO_REUSE if no_reuse else 0) | \
             (TN_FLAG_SIMPLE_KERNELS if simple else 0) | \
-            (TN_FLAG_PERSISTENT if persistent else 0) | (0 if chains else TN_FLAG_NO_CHAIN)
+            (TN_FLAG_PERSISTENT if persistent else 0) | (0 if chains else TN_FLAG_NO_CHAIN) | \
+            (0 if chain_mfma else TN_FLAG_CHAIN_VALU) | \
+            (0 if chain_fused else TN_FLAG_CHAIN_STEPWISE)
         opts.gemm_config = gemm_config
         entries = load_tune_table() if tune == "default" else (tune or [])
         tarr, t_p = _i32([x for e in entries for x in e] or [0])
@@ -209,6 +214,7 @@ class Plan:
         self.open_ids = list(open_ids)
         self.sliced = list(sliced)
         self.precision = precision
+        self.chain_valu = not chain_mfma
         self._ws = None
         self._ws_bwd = None
 

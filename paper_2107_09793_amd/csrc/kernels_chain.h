@@ -36,7 +36,8 @@ constexpr int kChainB = 1024;   // staged small-operand elements, all steps
 struct ChainStepArgs {
   const float2* B;
   int32_t nk, nn, nrow, nbb;                  // summed / new / row bits, batch bits of B
-  int32_t kslot[4], nslot[4], kB[4], nB[4];   // LDS slots and B strides of k and n bits
+  int32_t mfma;                               // run on the matrix cores (nk>=2, nn>=3, nrow>=4)
+  int32_t kslot[8], nslot[8], kB[8], nB[8];   // LDS slots and B strides of k and n bits
   int32_t rslot[kChainTile];                  // LDS slots of the row bits
   int32_t bB[kChainTile], bpas[kChainTile];   // batch bits: B stride, tile-number bit
 };
@@ -53,24 +54,53 @@ struct ChainArgs {
   ChainStepArgs st[kChainSteps];
 };
 
+// The arguments are read in place from the kernel-argument segment (constant
+// address space): every index into them is uniform, so they come in through
+// scalar loads and no private copy of the structure is made.
+#define TNK_KARG __attribute__((address_space(4)))
+typedef const TNK_KARG int32_t karg_i32;
+typedef const TNK_KARG ChainStepArgs karg_step;
+typedef const TNK_KARG ChainArgs karg_chain;
+
 // sum_j bit_j(idx) << s[j] over bits [lo, hi)
-__device__ __forceinline__ int64_t chain_off(uint64_t idx, const int32_t* s, int lo, int hi) {
+__device__ __forceinline__ int64_t chain_off(uint64_t idx, karg_i32* s, int lo, int hi) {
   int64_t off = 0;
 #pragma unroll 1
   for (int j = lo; j < hi; ++j) off += (int64_t)((idx >> j) & 1ull) << s[j];
   return off;
 }
 
-__device__ __forceinline__ int32_t chain_slot(uint32_t idx, const int32_t* s, int lo, int hi) {
+__device__ __forceinline__ int32_t chain_slot(uint32_t idx, karg_i32* s, int lo, int hi) {
   int32_t off = 0;
 #pragma unroll 1
   for (int j = lo; j < hi; ++j) off |= (int32_t)((idx >> j) & 1u) << s[j];
   return off;
 }
 
+// LDS positions are XOR-swizzled: bits 5..11 of a slot index are folded into
+// bits 0..4 (the bank of an 8-byte element), so lanes whose positions differ
+// only in high slots do not all hit one bank.  The map is XOR-linear and only
+// changes bits 0..4, hence a bijection of every 2^TB buffer, and it commutes
+// with assembling a position from disjoint bit groups.
+__device__ __forceinline__ int32_t chain_swz(int32_t x) {
+  return x ^ (((x >> 5) ^ (x >> 9)) & 31);
+}
+
+// Per-workgroup tables, built once before the tile loop: everything that
+// does not depend on the tile.
+template <int TB>
+struct ChainTables {
+  static constexpr int E = TB > 8 ? 1 << (TB - 8) : 1;
+  int64_t ein[E], eout[E];          // HBM offsets of tile element bits 8..
+  int32_t lin[E], lout[E];          // their LDS positions
+  int32_t boff[kChainB];            // small-operand offsets of staged entries (no batch part)
+  int32_t rhi[kChainSteps][64];     // row bits >= 8 (vector steps) or >= 4 (matrix steps)
+};
+
 // small operand of a step staged as [n][k]
 template <int NK, int NN>
-__device__ __forceinline__ void chain_rows(const ChainStepArgs& S, float2* buf, const float2* sB) {
+__device__ __forceinline__ void chain_rows(karg_step& S, float2* buf, const float2* sB,
+                                           const int32_t* rhi) {
   constexpr int K = 1 << NK, N = 1 << NN;
   int32_t koff[K];
 #pragma unroll
@@ -84,15 +114,19 @@ __device__ __forceinline__ void chain_rows(const ChainStepArgs& S, float2* buf, 
 #pragma unroll
   for (int j = 0; j < NN; ++j) ns[j] = S.nslot[j];
   const int nrow = S.nrow;
-  const int lo = nrow < 8 ? nrow : 8;
   const uint32_t rows = 1u << nrow;
-  const int32_t rlo = chain_slot(threadIdx.x, S.rslot, 0, lo);
+  int32_t rlo = 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    if (j < nrow) rlo |= ((threadIdx.x >> j) & 1) << S.rslot[j];
   for (uint32_t r0 = 0; r0 < rows; r0 += 256) {
     if (r0 + threadIdx.x >= rows) break;
-    const int32_t base = rlo | chain_slot(r0, S.rslot, 8, nrow);
+    const int32_t base = rlo | rhi[r0 >> 8];
     float2 a[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) a[k] = buf[base | koff[k]];
+    for (int k = 0; k < K; ++k) a[k] = buf[chain_swz(base | koff[k])];
+    // one output column at a time: its K small-operand values are LDS
+    // broadcasts (every lane reads the same address)
 #pragma unroll 1
     for (int n = 0; n < N; ++n) {
       int32_t no = 0;
@@ -102,17 +136,126 @@ __device__ __forceinline__ void chain_rows(const ChainStepArgs& S, float2* buf, 
       float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
       for (int k = 0; k < K; ++k) cfma(acc, a[k], bn[k]);
-      buf[base | no] = acc;
+      buf[chain_swz(base | no)] = acc;
     }
   }
 }
 
-__device__ __forceinline__ void chain_step(const ChainStepArgs& S, float2* buf, const float2* sB) {
+// The same step on the FP32 matrix cores (v_mfma_f32_16x16x4f32) for
+// 4 <= 2^nk <= 64 summed and 8 <= 2^nn <= 32 new values, 2^(nk+nn) <= 512
+// (the plan's limit): the complex product is the real one of A' (rows x 2K,
+// re/im interleaved) and B' = [[Br, Bi], [-Bi, Br]] (2K x 2N).  A wave takes
+// 16 rows at a time.  In k step s, lane group g = lane / 16 supplies complex
+// k = g K/4 + s/2, real part s % 2, so a lane reads its row's K/4 values
+// once; B' is held in registers for the step.  Output lane layout: rows
+// 4 (lane / 16) + r, real column lane % 16 of the 16-column block.  The
+// row's values are all read before any is written, and 16-row blocks of
+// different waves are disjoint, so the step runs in place.  Sums run in the
+// matrix core's order, not the stream kernel's.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+template <int NK, int NN>
+__device__ __forceinline__ void chain_rows_mfma(karg_step& S, float2* buf, const float2* sB,
+                                                const int32_t* rhi) {
+  constexpr int K = 1 << NK, N = 1 << NN;
+  constexpr int KG = K / 4;          // complex k per lane group
+  constexpr int KS = K / 2;          // k steps of 4 real values
+  constexpr int CB = N / 8;          // 16-column blocks of the real output
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  // B' for this lane: column 16 cb + li, k steps 0..KS-1
+  float bv[CB][KS];
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb) {
+    const int jj = 16 * cb + li, n = jj >> 1, q = jj & 1;
+#pragma unroll
+    for (int j = 0; j < KG; ++j) {
+      const float2 b = sB[n * K + g * KG + j];
+      bv[cb][2 * j] = q ? b.y : b.x;         // real part of a: (Br, Bi)
+      bv[cb][2 * j + 1] = q ? b.x : -b.y;    // imaginary part of a: (-Bi, Br)
+    }
+  }
+  int32_t ks[NK];
+#pragma unroll
+  for (int t = 0; t < NK; ++t) ks[t] = S.kslot[t];
+  int32_t koff[KG];
+#pragma unroll
+  for (int j = 0; j < KG; ++j) {
+    const int k = g * KG + j;
+    int32_t o = 0;
+#pragma unroll
+    for (int t = 0; t < NK; ++t) o |= ((k >> t) & 1) << ks[t];
+    koff[j] = o;
+  }
+  int32_t noff[CB];
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb) {
+    const int n = (16 * cb + li) >> 1;
+    int32_t o = 0;
+#pragma unroll
+    for (int t = 0; t < NN; ++t) o |= ((n >> t) & 1) << S.nslot[t];
+    noff[cb] = o;
+  }
+  // in-block row offsets: the lane's input row li, its output rows 4 g + r
+  int32_t rs[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) rs[t] = S.rslot[t];
+  int32_t in_lo = 0;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) in_lo |= ((li >> t) & 1) << rs[t];
+  int32_t out_lo[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    int32_t o = 0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) o |= (((4 * g + r) >> t) & 1) << rs[t];
+    out_lo[r] = o;
+  }
+  const uint32_t blocks = 1u << (S.nrow - 4);
+  float* fb = reinterpret_cast<float*>(buf);
+  const int q = li & 1;
+  for (uint32_t rb = wave; rb < blocks; rb += 4) {
+    const int32_t hi = rhi[rb];
+    float2 a[KG];
+#pragma unroll
+    for (int j = 0; j < KG; ++j) a[j] = buf[chain_swz(hi | in_lo | koff[j])];
+    floatx4 acc[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) acc[cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s2 = 0; s2 < KS; ++s2) {
+      const float av = (s2 & 1) ? a[s2 >> 1].y : a[s2 >> 1].x;
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb)
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[cb][s2], acc[cb], 0, 0, 0);
+    }
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) fb[2 * chain_swz(hi | out_lo[r] | noff[cb]) + q] = acc[cb][r];
+  }
+}
+
+__device__ __forceinline__ void chain_step(karg_step& S, float2* buf, const float2* sB,
+                                           const int32_t* rhi) {
+  if (S.mfma) {
+#define TNK_CHAIN_MFMA(A, B)                   \
+  if (S.nk == A && S.nn == B) {                \
+    chain_rows_mfma<A, B>(S, buf, sB, rhi);    \
+    return;                                    \
+  }
+    TNK_CHAIN_MFMA(2, 3) TNK_CHAIN_MFMA(2, 4) TNK_CHAIN_MFMA(2, 5)
+    TNK_CHAIN_MFMA(3, 3) TNK_CHAIN_MFMA(3, 4) TNK_CHAIN_MFMA(3, 5)
+    TNK_CHAIN_MFMA(4, 3) TNK_CHAIN_MFMA(4, 4) TNK_CHAIN_MFMA(4, 5)
+    TNK_CHAIN_MFMA(5, 3) TNK_CHAIN_MFMA(5, 4)
+    TNK_CHAIN_MFMA(6, 3)
+#undef TNK_CHAIN_MFMA
+  }
   // the per-step stream kernel covers nk, nn in 0..4; so does the chain
-#define TNK_CHAIN_CASE(A, B)          \
-  if (S.nk == A && S.nn == B) {       \
-    chain_rows<A, B>(S, buf, sB);     \
-    return;                           \
+#define TNK_CHAIN_CASE(A, B)                \
+  if (S.nk == A && S.nn == B) {             \
+    chain_rows<A, B>(S, buf, sB, rhi);      \
+    return;                                 \
   }
 #define TNK_CHAIN_ROW(A) \
   TNK_CHAIN_CASE(A, 0) TNK_CHAIN_CASE(A, 1) TNK_CHAIN_CASE(A, 2) TNK_CHAIN_CASE(A, 3) TNK_CHAIN_CASE(A, 4)
@@ -122,58 +265,101 @@ __device__ __forceinline__ void chain_step(const ChainStepArgs& S, float2* buf, 
 }
 
 template <int TB>
-__global__ void __launch_bounds__(256) k_chain(ChainArgs g) {
+__global__ void __launch_bounds__(256) k_chain(ChainArgs) {
+  using Tab = ChainTables<TB>;
+  constexpr int E = Tab::E;                        // tile elements per thread, at most
+  constexpr int EB = E < 8 ? E : 8;                // loads in flight per batch
   __shared__ float2 buf[1 << TB];
   __shared__ float2 sB[kChainB];
+  __shared__ Tab tab;
+  karg_chain& g = *(karg_chain*)__builtin_amdgcn_kernarg_segment_ptr();
   const int tid = threadIdx.x;
-  const uint64_t n_tiles = 1ull << g.npas;
-  // per-thread parts of the load / store offsets (tile bits 0..7 = thread id)
-  const int lo_in = g.tin < 8 ? g.tin : 8, lo_out = g.tout < 8 ? g.tout : 8;
+  const int nsteps = g.nsteps, npas = g.npas, tin = g.tin, tout = g.tout;
+  // --- tables -------------------------------------------------------------
+  if (tid < E) {
+    const uint32_t e = (uint32_t)tid << 8;
+    tab.ein[tid] = chain_off(e, g.in_log2, 8, tin);
+    tab.eout[tid] = chain_off(e, g.out_log2, 8, tout);
+    tab.lin[tid] = chain_slot(e, g.in_slot, 8, tin);
+    tab.lout[tid] = chain_slot(e, g.out_slot, 8, tout);
+  }
+  {
+    int off = 0;
+    for (int q = 0; q < nsteps; ++q) {
+      karg_step& S = g.st[q];
+      const int nk = S.nk, nn = S.nn, cnt = 1 << (nk + nn);
+      for (int i = tid; i < cnt; i += 256) {
+        const int n = i >> nk, k = i & ((1 << nk) - 1);
+        tab.boff[off + i] = (int32_t)(chain_off(k, S.kB, 0, nk) + chain_off(n, S.nB, 0, nn));
+      }
+      off += cnt;
+      // high row parts: per 256-row group (vector steps) or 16-row block
+      const int lo = S.mfma ? 4 : 8;
+      const int nhi = S.nrow > lo ? 1 << (S.nrow - lo) : 1;
+      for (int i = tid; i < nhi; i += 256) tab.rhi[q][i] = chain_slot((uint32_t)i << lo, S.rslot, lo, S.nrow);
+    }
+  }
+  // tile numbers: t = blockIdx.x + m * gridDim.x with gridDim.x a power of two,
+  // so the low tile bits are this workgroup's and only the high ones vary
+  const int lg = 31 - __builtin_clz(gridDim.x);
+  const int64_t bx_lo = chain_off(blockIdx.x, g.pas_in, 0, lg < npas ? lg : npas);
+  const int64_t by_lo = chain_off(blockIdx.x, g.pas_out, 0, lg < npas ? lg : npas);
+  const int lo_in = tin < 8 ? tin : 8, lo_out = tout < 8 ? tout : 8;
   const int64_t xin_lo = chain_off(tid, g.in_log2, 0, lo_in);
   const int32_t lin_lo = chain_slot(tid, g.in_slot, 0, lo_in);
   const int64_t yout_lo = chain_off(tid, g.out_log2, 0, lo_out);
   const int32_t lout_lo = chain_slot(tid, g.out_slot, 0, lo_out);
-  const uint32_t n_in = 1u << g.tin, n_out = 1u << g.tout;
+  const uint32_t n_in = 1u << tin, n_out = 1u << tout;
+  const uint64_t n_tiles = 1ull << npas;
+  __syncthreads();
   bool staged = false;
   for (uint64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-    const int64_t bx = chain_off(t, g.pas_in, 0, g.npas);
-    const int64_t by = chain_off(t, g.pas_out, 0, g.npas);
+    const int64_t bx = bx_lo + chain_off(t, g.pas_in, lg, npas);
+    const int64_t by = by_lo + chain_off(t, g.pas_out, lg, npas);
     // small operands, [n][k] per step
     if (!staged || g.b_per_tile) {
       int off = 0;
-      for (int q = 0; q < g.nsteps; ++q) {
-        const ChainStepArgs& S = g.st[q];
-        const int nk = S.nk, nn = S.nn, cnt = 1 << (nk + nn);
+      for (int q = 0; q < nsteps; ++q) {
+        karg_step& S = g.st[q];
+        const int cnt = 1 << (S.nk + S.nn);
         int64_t bb = 0;
 #pragma unroll 1
         for (int j = 0; j < S.nbb; ++j) bb += (int64_t)((t >> S.bpas[j]) & 1ull) << S.bB[j];
-        for (int i = tid; i < cnt; i += 256) {
-          const int n = i >> nk, k = i & ((1 << nk) - 1);
-          sB[off + i] = S.B[bb + chain_off(k, S.kB, 0, nk) + chain_off(n, S.nB, 0, nn)];
-        }
+        const float2* B = S.B + bb;
+        for (int i = tid; i < cnt; i += 256) sB[off + i] = B[tab.boff[off + i]];
         off += cnt;
       }
       staged = true;
     }
-    // load the input tile
-    for (uint32_t r0 = 0; r0 < n_in; r0 += 256) {
-      if (r0 + tid >= n_in) break;
-      const int64_t go = bx + xin_lo + chain_off(r0, g.in_log2, 8, g.tin);
-      buf[lin_lo | chain_slot(r0, g.in_slot, 8, g.tin)] = g.X[go];
+    // load the input tile, eight loads per thread in flight at a time
+#pragma unroll
+    for (int e0 = 0; e0 < E; e0 += EB) {
+      float2 v[EB];
+#pragma unroll
+      for (int e = 0; e < EB; ++e)
+        if ((uint32_t)((e0 + e) << 8) + tid < n_in) v[e] = g.X[bx + xin_lo + tab.ein[e0 + e]];
+#pragma unroll
+      for (int e = 0; e < EB; ++e)
+        if ((uint32_t)((e0 + e) << 8) + tid < n_in) buf[chain_swz(lin_lo | tab.lin[e0 + e])] = v[e];
     }
     __syncthreads();
     int off = 0;
-    for (int q = 0; q < g.nsteps; ++q) {
-      const ChainStepArgs& S = g.st[q];
-      chain_step(S, buf, sB + off);
+    for (int q = 0; q < nsteps; ++q) {
+      karg_step& S = g.st[q];
+      chain_step(S, buf, sB + off, tab.rhi[q]);
       off += 1 << (S.nk + S.nn);
       __syncthreads();
     }
     // store the output tile
-    for (uint32_t r0 = 0; r0 < n_out; r0 += 256) {
-      if (r0 + tid >= n_out) break;
-      const int64_t go = by + yout_lo + chain_off(r0, g.out_log2, 8, g.tout);
-      g.Y[go] = buf[lout_lo | chain_slot(r0, g.out_slot, 8, g.tout)];
+#pragma unroll
+    for (int e0 = 0; e0 < E; e0 += EB) {
+      float2 v[EB];
+#pragma unroll
+      for (int e = 0; e < EB; ++e)
+        if ((uint32_t)((e0 + e) << 8) + tid < n_out) v[e] = buf[chain_swz(lout_lo | tab.lout[e0 + e])];
+#pragma unroll
+      for (int e = 0; e < EB; ++e)
+        if ((uint32_t)((e0 + e) << 8) + tid < n_out) g.Y[by + yout_lo + tab.eout[e0 + e]] = v[e];
     }
     __syncthreads();
   }

@@ -109,6 +109,11 @@ struct StepBits {  // global bit ids of a step's classes, in stride-array order
   Bits batch, M, N, K;
 };
 
+// Chain steps the matrix-core path covers (see kernels_chain.h).
+bool chain_mfma_shape(int nk, int nn) {
+  return nk >= 2 && nk <= 6 && nn >= 3 && nn <= 5 && nk + nn <= 9;
+}
+
 // Tile of a chain candidate first..last (see ChainGroup); returns false when
 // it does not fit the LDS tile or a summed / batch bit is misplaced.
 bool build_chain(const Plan& p, const std::vector<Layout>& lay, const std::vector<StepBits>& sb,
@@ -177,6 +182,17 @@ bool build_chain(const Plan& p, const std::vector<Layout>& lay, const std::vecto
     if (ok && max_live + (int)ptile.size() <= kChainTileBits) break;
   }
   if (want < 3) return false;
+  // then further passive bits, lowest input stride first, until the tile has
+  // its full size: every thread of the workgroup gets rows to work on and
+  // the per-tile costs are spread over more elements
+  for (int32_t b : xo) {
+    if (max_live + (int)ptile.size() >= kChainTileBits) break;
+    if (std::binary_search(in_act.begin(), in_act.end(), b) ||
+        std::binary_search(batch_all.begin(), batch_all.end(), b) ||
+        std::find(ptile.begin(), ptile.end(), b) != ptile.end())
+      continue;
+    ptile.push_back(b);
+  }
   std::sort(ptile.begin(), ptile.end());
   const Bits pt = minus(pas, ptile);   // passive bits that enumerate tiles
   if ((int)pt.size() > kChainPassive) return false;
@@ -220,6 +236,8 @@ bool build_chain(const Plan& p, const std::vector<Layout>& lay, const std::vecto
     std::sort(rs.begin(), rs.end());
     d.rslot = rs;
     d.nrow = (int32_t)rs.size();
+    // shapes only the matrix-core step runs need 16-row blocks
+    if ((sb[k].K.size() > 4 || sb[k].N.size() > 4) && d.nrow < 4) return false;
     d.kB = S.kB;
     d.nB = S.nB;
     d.bB = S.bB;
@@ -307,7 +325,30 @@ int32_t choose_tile(const Plan& p, int nm, int nn, int nk) {
 }
 
 // Build schedule for a given outer set; fills steps, sched, memory, stats.
+static void schedule_pass(Plan& p);
+
+// Two planning passes when chains are on: the first finds the chains, the
+// second lays out every chain input with the bits its chain sums over lowest
+// (and forms the chains again on those layouts).  Results of stream steps put
+// their new (column) bits lowest when chains are on, so a chain's output
+// tile -- the bits the chain created -- is one contiguous block.
 static void schedule(Plan& p) {
+  p.chain_in_low.clear();
+  schedule_pass(p);
+  if (p.chains.empty()) return;
+  for (const ChainGroup& g : p.chains) {
+    const int X = p.steps[g.first].a;
+    if (X < p.n_tensors) continue;   // leaf layouts are the caller's
+    Bits in;
+    for (int k = g.first; k <= g.last; ++k)
+      for (int32_t b : p.chain_sum_bits[k]) in.push_back(b);
+    std::sort(in.begin(), in.end());
+    p.chain_in_low[X] = inter(in, p.node_ebits[X]);
+  }
+  schedule_pass(p);
+}
+
+static void schedule_pass(Plan& p) {
   const int n = p.n_tensors;
   const int nsteps = n - 1;
   const int nn_nodes = n + nsteps;
@@ -346,6 +387,7 @@ static void schedule(Plan& p) {
 
   p.steps.assign(nsteps, StepDesc());
   std::vector<StepBits> sbits(nsteps);
+  p.chain_sum_bits.assign(nsteps, {});
   for (int k = 0; k < nsteps; ++k) {
     int a = p.path[2 * k], b = p.path[2 * k + 1], v = n + k;
     StepDesc& S = p.steps[k];
@@ -370,16 +412,29 @@ static void schedule(Plan& p) {
     K = by(K, lay[a]);
     int nb = (int)batch.size(), nm = (int)M.size(), nnb = (int)N.size(), nk = (int)K.size();
     sbits[k] = StepBits{batch, M, N, K};
+    p.chain_sum_bits[k] = K;
     S.kind = choose_kind(nb, nm, nnb, nk, p.flags, &S.splitk_chunks, &S.scratch_bytes);
     // result layout, least significant first.  GEMM tiles store 16 consecutive
     // columns per half-wave: columns, rows, batch.  The stream kernel runs one
     // row per lane: rows, columns, batch.
     Bits clayout;
-    const Bits& lo = S.kind == KIND_STREAM ? M : N;
-    const Bits& mid = S.kind == KIND_STREAM ? N : M;
+    const bool rows_low = S.kind == KIND_STREAM && (p.flags & 8u);   // no chains
+    const Bits& lo = rows_low ? M : N;
+    const Bits& mid = rows_low ? N : M;
     clayout.insert(clayout.end(), lo.begin(), lo.end());
     clayout.insert(clayout.end(), mid.begin(), mid.end());
     clayout.insert(clayout.end(), batch.begin(), batch.end());
+    auto ov = p.chain_in_low.find(v);
+    if (ov != p.chain_in_low.end()) {
+      // input of a chain (found by an earlier planning pass): the bits that
+      // chain sums over lowest, so its tiles are read as contiguous blocks
+      Bits want = ov->second, first, rest;
+      std::sort(want.begin(), want.end());
+      for (int32_t x : clayout)
+        (std::binary_search(want.begin(), want.end(), x) ? first : rest).push_back(x);
+      clayout = first;
+      clayout.insert(clayout.end(), rest.begin(), rest.end());
+    }
     for (size_t i = 0; i < clayout.size(); ++i) lay[v].s[clayout[i]] = (int8_t)i;
     p.node_layout[v] = clayout;
     p.node_ebits[v] = unite(unite(batch, M), N);
@@ -425,9 +480,17 @@ static void schedule(Plan& p) {
   // previous result as its large operand, grown while the tile fits
   p.chains.clear();
   if (!(p.flags & 8u)) {
+    // vector-unit chain steps: 2^nk, 2^nn <= 16 (the stream kernel's
+    // shapes); matrix-core chain steps also take GEMM-kind steps with
+    // 4 <= 2^nk <= 64, 8 <= 2^nn <= 32 and a small operand of at most 2^9
+    // entries (register budget of the kernel)
+    const bool mfma = !(p.flags & 32u);
     auto fusable = [&](int k) {
       const StepDesc& S = p.steps[k];
-      return S.kind == KIND_STREAM && !S.small && S.kA.size() <= 4 && S.nB.size() <= 4;
+      if (S.small) return false;
+      const int nk = (int)S.kA.size(), nn = (int)S.nB.size();
+      if (S.kind == KIND_STREAM && nk <= 4 && nn <= 4) return true;
+      return mfma && (S.kind == KIND_STREAM || S.kind == KIND_GEMM) && chain_mfma_shape(nk, nn);
     };
     int k = 0;
     while (k < nsteps) {
@@ -517,7 +580,8 @@ static void schedule(Plan& p) {
     StepDesc& S = p.steps[sk];
     // a chain runs at the position of its last step: one result, and the
     // inputs of all its steps released there
-    if (S.chain >= 0 && p.chains[S.chain].last != sk) {
+    const bool fused = S.chain >= 0 && !(p.flags & 64u);
+    if (fused && p.chains[S.chain].last != sk) {
       S.c_off = -1;
       continue;
     }
@@ -525,7 +589,7 @@ static void schedule(Plan& p) {
     p.bytes_no_deletion += align_up(S.c_bytes, 256);
     p.scratch_bytes = std::max(p.scratch_bytes, S.scratch_bytes);
     std::vector<int32_t> ins;
-    if (S.chain >= 0) {
+    if (fused) {
       const ChainGroup& g = p.chains[S.chain];
       ins.push_back(p.steps[g.first].a);
       for (int q = g.first; q <= g.last; ++q) ins.push_back(p.steps[q].b);
@@ -616,8 +680,9 @@ static void schedule(Plan& p) {
     int32_t d = saved - 2;
     p.n_launches -= g.phase ? (int32_t)iters * d : d;
   }
-  // chains: one launch for all their steps
+  // chains: one launch for all their steps (unless launched step by step)
   for (const ChainGroup& g : p.chains) {
+    if (p.flags & 64u) break;
     int32_t d = g.last - g.first;
     p.n_launches -= g.phase ? (int32_t)iters * d : d;
   }

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -112,6 +113,8 @@ struct Plan {
   int32_t n_phase0 = 0;                      // sched[0 .. n_phase0) run once
   std::vector<Segment> segments;             // persistent launches
   std::vector<ChainGroup> chains;            // fused chains of stream steps
+  std::map<int32_t, std::vector<int32_t>> chain_in_low;  // chain input node -> bits to put lowest
+  std::vector<std::vector<int32_t>> chain_sum_bits;      // summed bits of each step
   int64_t persist_bytes = 0;                 // control region for one tn_contract
 
   // outer / resident split (whole sliced indices)

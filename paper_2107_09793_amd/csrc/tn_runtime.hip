@@ -324,6 +324,9 @@ tn_status run_chain(const Ctx& c, const tn::ChainGroup& g, uint64_t outer_val,
   for (size_t q = 0; q < g.st.size(); ++q) {
     const tn::ChainStepDesc& d = g.st[q];
     tnk::ChainStepArgs& t = a.st[q];
+    if (d.kslot.size() > 6 || d.nslot.size() > 5 || d.rslot.size() > (size_t)tnk::kChainTile ||
+        d.bB.size() > (size_t)tnk::kChainTile)
+      return fail(TN_E_INVALID, "chain step exceeds its descriptor");
     t.B = node_ptr(c, p.steps[d.step].b, outer_val);
     t.nk = (int8_t)d.kslot.size();
     t.nn = (int8_t)d.nslot.size();
@@ -343,6 +346,13 @@ tn_status run_chain(const Ctx& c, const tn::ChainGroup& g, uint64_t outer_val,
       t.bpas[j] = d.bpas[j];
     }
     if (!d.bB.empty()) a.b_per_tile = 1;
+    // the matrix-core step covers 2 <= nk <= 6, 3 <= nn <= 5, nk + nn <= 9
+    const bool mshape = t.nk >= 2 && t.nk <= 6 && t.nn >= 3 && t.nn <= 5 && t.nk + t.nn <= 9;
+    t.mfma = !(p.flags & 32u) && mshape && t.nrow >= 4;
+    if ((t.nk > 4 || t.nn > 4) && !t.mfma)
+      return fail(TN_E_INVALID, "chain step shape needs the matrix-core path");
+    if (t.mfma ? t.nrow > 10 : t.nrow > 14)   // row-part table: 64 entries per step
+      return fail(TN_E_INVALID, "chain step has more rows than its table");
     total += 1 << (t.nk + t.nn);
   }
   a.b_total = total;
@@ -351,6 +361,9 @@ tn_status run_chain(const Ctx& c, const tn::ChainGroup& g, uint64_t outer_val,
   const uint64_t n_tiles = 1ull << a.npas;
   const unsigned grid = (unsigned)std::min<uint64_t>(n_tiles, 1u << 16);
   bool timed = false;
+  static_assert(sizeof(a.st[0].kslot) / sizeof(a.st[0].kslot[0]) >= 6 &&
+                    sizeof(a.st[0].nslot) / sizeof(a.st[0].nslot[0]) >= 5,
+                "chain step arrays hold the largest summed / new bit counts");
   if (probe && !probe->done)
     for (int k = g.first; k <= g.last; ++k) timed |= probe->step == k;
   if (timed) TN_HIP_CHECK(hipEventRecord(probe->start, c.st));
@@ -585,6 +598,8 @@ tn_status tn_plan_chain(tn_plan_t plan, int32_t i, tn_chain_info* out) {
   for (size_t q = 0; q < g.st.size(); ++q) {
     const tn::ChainStepDesc& d = g.st[q];
     tn_chain_step_info& t = out->st[q];
+    if (d.kslot.size() > 8 || d.nslot.size() > 8 || d.rslot.size() > 12 || d.bB.size() > 12)
+      return fail(TN_E_INVALID, "chain step exceeds its descriptor");
     t.step = d.step;
     t.nrow = d.nrow;
     t.nk = (int32_t)d.kslot.size();
@@ -692,7 +707,7 @@ static tn_status contract_impl(tn_plan_t plan, const void* const* leaves, const 
         continue;
       }
       const tn::StepDesc& S = p.steps[p.sched[i]];
-      if (S.chain >= 0) {   // a chain runs at the position of its last step
+      if (S.chain >= 0 && !(p.flags & 64u)) {   // a chain runs at the position of its last step
         const tn::ChainGroup& g = p.chains[S.chain];
         if (g.last == p.sched[i]) {
           tn_status s = run_chain(c, g, it, probe);

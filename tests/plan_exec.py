@@ -62,7 +62,9 @@ def execute(plan, leaves, dtype=np.complex128):
             [k for k in range(n - 1) if steps[k]["phase"] == 1]
     for k in order:
         s = steps[k]
-        if s["chain"] >= 0:
+        stepwise = s["chain"] >= 0 and steps[chains[s["chain"]]["first"]]["c_offset"] != -1 \
+            if chains else False
+        if s["chain"] >= 0 and not stepwise:
             ch = chains[s["chain"]]
             if k != ch["last"]:
                 assert s["c_offset"] == -1

@@ -1,7 +1,9 @@
 """Fused chains of stream steps on the GPU against the same steps launched
-one by one: each output value is formed by the same complex FMAs in the same
-order either way, so results must agree bit for bit; both are also checked
-against the complex128 oracle (1e-5)."""
+one by one.  With the chain on the vector units each output value is formed
+by the same complex FMAs in the same order either way, so results must agree
+bit for bit.  With the matrix-core chain steps (the default) the sums run in
+another order, so both are checked against the complex128 oracle (1e-5 of
+the rms slice value)."""
 
 import numpy as np
 import pytest
@@ -29,22 +31,27 @@ def _batch_net(seed, rows, cols, depth, batch, n_slice):
 
 
 @pytest.mark.parametrize("cfg", [(3, 4, 4, 12, 16, 2), (7, 4, 4, 14, 32, 2), (9, 4, 4, 10, 16, 3),
-                                 (3, 4, 5, 12, 16, 2)])
+                                 (3, 4, 5, 12, 16, 2), (7, 4, 5, 14, 32, 2), (5, 4, 5, 12, 64, 2)])
 def test_chain_bitwise_equals_per_step(cfg):
     from paper_2107_09793_amd import Plan
     dev = _dev()
     tn, p, sl = _batch_net(*cfg)
     leaves = [torch.from_numpy(t.astype(np.complex64)).to(dev) for t in tn.tensors]
-    fused = Plan.from_network(tn, p, sl, persistent=False)
-    plain = Plan.from_network(tn, p, sl, persistent=False, chains=False)
+    fused = Plan.from_network(tn, p, sl, chain_mfma=False)
+    plain = Plan.from_network(tn, p, sl, chain_mfma=False, chain_fused=False)
+    mfma = Plan.from_network(tn, p, sl)
     assert fused.info()["n_chains"] > 0
+    assert plain.info()["n_chains"] == fused.info()["n_chains"]
+    assert plain.info()["n_launches"] > fused.info()["n_launches"]
     a = fused.contract(leaves, per_slice=True).cpu().numpy()
     b = plain.contract(leaves, per_slice=True).cpu().numpy()
+    c = mfma.contract(leaves, per_slice=True).cpu().numpy()
     assert np.array_equal(a, b)
     ref = tn_oracle.contract(tn.tensors, tn.labels, tn.dims, tn.open, p, sl, per_slice=True)
     ref = np.asarray(ref).reshape(a.shape)
     rms = np.sqrt(np.mean(np.abs(ref) ** 2))
     assert np.max(np.abs(a - ref)) <= 1e-5 * rms
+    assert np.max(np.abs(c - ref)) <= 1e-5 * rms
 
 
 def test_chain_sliced_workload_bitwise():
@@ -55,10 +62,16 @@ def test_chain_sliced_workload_bitwise():
     w = workloads.build("sliced", seed=0)
     leaves = [torch.from_numpy(np.ascontiguousarray(t, dtype=np.complex64)).to(dev)
               for t in w.tn.tensors]
-    fused = Plan.from_network(w.tn, w.path, w.sliced)
-    plain = Plan.from_network(w.tn, w.path, w.sliced, chains=False)
+    fused = Plan.from_network(w.tn, w.path, w.sliced, chain_mfma=False)
+    plain = Plan.from_network(w.tn, w.path, w.sliced, chain_mfma=False, chain_fused=False)
     a = fused.contract(leaves, per_slice=True).cpu().numpy()
     del fused
     torch.cuda.empty_cache()
     b = plain.contract(leaves, per_slice=True).cpu().numpy()
     assert np.array_equal(a, b)
+    del plain
+    torch.cuda.empty_cache()
+    mfma = Plan.from_network(w.tn, w.path, w.sliced)
+    c = mfma.contract(leaves, per_slice=True).cpu().numpy()
+    rms = np.sqrt(np.mean(np.abs(b) ** 2))
+    assert np.max(np.abs(c - b)) <= 1e-5 * rms

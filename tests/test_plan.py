@@ -170,7 +170,7 @@ def _batch_net(seed, rows, cols, depth, batch, n_slice):
     return tn, p, sl
 
 
-@pytest.mark.parametrize("cfg", [(3, 4, 4, 12, 16, 2), (7, 4, 4, 14, 32, 2), (9, 4, 4, 10, 16, 3)])
+@pytest.mark.parametrize("cfg", [(7, 4, 4, 14, 32, 2), (9, 4, 4, 10, 16, 3), (7, 4, 5, 14, 32, 2)])
 def test_cpu_execution_of_fused_chains_matches_oracle(cfg):
     """Chains (consecutive stream steps run as one tiled pass) executed on the
     CPU from their descriptors: tile loads through the input strides, LDS
@@ -184,7 +184,6 @@ def test_cpu_execution_of_fused_chains_matches_oracle(cfg):
     chains = pl.chains()
     assert info["n_chains"] == len(chains) > 0
     assert any(ch["pas_in"] for ch in chains)
-    assert any(d["bB"] for ch in chains for d in ch["st"])
     steps = pl.steps()
     for ch in chains:
         assert 2 <= len(ch["st"]) <= 8 and ch["tile_bits"] <= 12
@@ -195,10 +194,53 @@ def test_cpu_execution_of_fused_chains_matches_oracle(cfg):
     got, _ = execute(pl, tn.tensors)
     ref = np.asarray(tn_oracle.contract(tn.tensors, tn.labels, tn.dims, tn.open, p, sl)).reshape(-1)
     assert np.allclose(got, ref, rtol=1e-12, atol=1e-13 * np.max(np.abs(ref)))
+    stepwise = Plan.from_network(tn, p, sl, chain_fused=False)
+    assert stepwise.info()["n_chains"] == info["n_chains"]
+    assert all(s["c_offset"] >= 0 for s in stepwise.steps())
+    got2, _ = execute(stepwise, tn.tensors)
+    assert np.allclose(got2, ref, rtol=1e-12, atol=1e-13 * np.max(np.abs(ref)))
     unfused = Plan.from_network(tn, p, sl, persistent=False, chains=False)
     assert unfused.info()["n_chains"] == 0
     assert unfused.info()["n_launches"] - info["n_launches"] == sum(
         ch["last"] - ch["first"] for ch in chains) * (1 << info["n_outer_bits"])
+
+
+def test_some_chain_selects_small_operands_by_batch_bits():
+    """Across the chain test networks, some chain step has batch bits (slice
+    or output bits held by both operands), which pick the small operand per
+    tile; the CPU execution above covers them."""
+    found = False
+    for cfg in [(7, 4, 4, 14, 32, 2), (9, 4, 4, 10, 16, 3), (7, 4, 5, 14, 32, 2)]:
+        tn, p, sl = _batch_net(*cfg)
+        pl = Plan.from_network(tn, p, sl)
+        found |= any(d["bB"] for ch in pl.chains() for d in ch["st"])
+    assert found
+
+
+def test_chain_descriptors_hold_wide_matrix_core_steps():
+    """GEMM-kind steps with up to 2^6 summed and 2^5 new values join chains
+    on the matrix-core path (not on the vector-unit path); their descriptors
+    carry every summed and new bit, and the CPU execution still matches."""
+    circ = circuits.grid_rqc(3, 4, 8, seed=2)
+    b = circuits.random_bitstrings(circ.n, 2, 8, 2)
+    tn = network.relabel_compact(network.circuit_network(circ, batch=b))
+    p = tpath.greedy_path(tn.labels, tn.dims, tn.open)
+    sl = slicing.greedy_slices(slicing.TreeSets(tn.labels, tn.dims, tn.open, p), n_slice=2)
+    pl = Plan(tn.labels, tn.dims, tn.open, p, sl)
+    steps = pl.steps()
+    wide = [(d, steps[d["step"]]) for ch in pl.chains() for d in ch["st"]
+            if steps[d["step"]]["nn"] > 4 or steps[d["step"]]["nk"] > 4]
+    assert wide
+    for d, s in wide:
+        assert len(d["kslot"]) == s["nk"] and len(d["nslot"]) == s["nn"] and d["nrow"] >= 4
+    valu = Plan(tn.labels, tn.dims, tn.open, p, sl, chain_mfma=False)
+    vsteps = valu.steps()
+    for ch in valu.chains():
+        for d in ch["st"]:
+            assert vsteps[d["step"]]["nk"] <= 4 and vsteps[d["step"]]["nn"] <= 4
+    got, _ = execute(pl, tn.tensors)
+    ref = np.asarray(tn_oracle.contract(tn.tensors, tn.labels, tn.dims, tn.open, p, sl)).reshape(-1)
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-13 * np.max(np.abs(ref)))
 
 
 def _live_ranges(pl):
