@@ -31,12 +31,15 @@ namespace tnk {
 constexpr int kChainSteps = 8;
 constexpr int kChainTile = 12;
 constexpr int kChainPas = 40;
-constexpr int kChainB = 1024;   // staged small-operand elements, all steps
+constexpr int kChainBF = 4096;  // staged small operands, all steps (floats)
+constexpr int kChainV = 512;    // complex entries staged for vector-unit steps
 
 struct ChainStepArgs {
   const float2* B;
   int32_t nk, nn, nrow, nbb;                  // summed / new / row bits, batch bits of B
-  int32_t mfma;                               // run on the matrix cores (nk>=2, nn>=3, nrow>=4)
+  int32_t mfma;                               // run on the matrix cores
+  int32_t boff0;                              // first staged float of this step
+  int32_t voff0;                              // first entry offset in the table (vector steps)
   int32_t kslot[8], nslot[8], kB[8], nB[8];   // LDS slots and B strides of k and n bits
   int32_t rslot[kChainTile];                  // LDS slots of the row bits
   int32_t bB[kChainTile], bpas[kChainTile];   // batch bits: B stride, tile-number bit
@@ -92,8 +95,8 @@ template <int TB>
 struct ChainTables {
   static constexpr int E = TB > 8 ? 1 << (TB - 8) : 1;
   int64_t ein[E], eout[E];          // HBM offsets of tile element bits 8..
-  int32_t lin[E], lout[E];          // their LDS positions
-  int32_t boff[kChainB];            // small-operand offsets of staged entries (no batch part)
+  int32_t lin[E], lout[E];          // their swizzled LDS byte offsets
+  int32_t boff[kChainV];            // small-operand offsets of staged entries (vector steps)
   int32_t rhi[kChainSteps][64];     // row bits >= 8 (vector steps) or >= 4 (matrix steps)
 };
 
@@ -143,11 +146,12 @@ __device__ __forceinline__ void chain_rows(karg_step& S, float2* buf, const floa
 
 // The same step on the FP32 matrix cores (v_mfma_f32_16x16x4f32) for
 // 4 <= 2^nk <= 64 summed and 8 <= 2^nn <= 32 new values, 2^(nk+nn) <= 512
-// (the plan's limit): the complex product is the real one of A' (rows x 2K,
+// (the plan's rule): the complex product is the real one of A' (rows x 2K,
 // re/im interleaved) and B' = [[Br, Bi], [-Bi, Br]] (2K x 2N).  A wave takes
 // 16 rows at a time.  In k step s, lane group g = lane / 16 supplies complex
 // k = g K/4 + s/2, real part s % 2, so a lane reads its row's K/4 values
-// once; B' is held in registers for the step.  Output lane layout: rows
+// once; B' is staged in LDS in the order the lanes read it (one float per
+// lane and instruction, consecutive across lanes).  Output lane layout: rows
 // 4 (lane / 16) + r, real column lane % 16 of the 16-column block.  The
 // row's values are all read before any is written, and 16-row blocks of
 // different waves are disjoint, so the step runs in place.  Sums run in the
@@ -155,7 +159,7 @@ __device__ __forceinline__ void chain_rows(karg_step& S, float2* buf, const floa
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 template <int NK, int NN>
-__device__ __forceinline__ void chain_rows_mfma(karg_step& S, float2* buf, const float2* sB,
+__device__ __forceinline__ void chain_rows_mfma(karg_step& S, float2* buf, const float* sBf,
                                                 const int32_t* rhi) {
   constexpr int K = 1 << NK, N = 1 << NN;
   constexpr int KG = K / 4;          // complex k per lane group
@@ -163,18 +167,8 @@ __device__ __forceinline__ void chain_rows_mfma(karg_step& S, float2* buf, const
   constexpr int CB = N / 8;          // 16-column blocks of the real output
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, li = lane & 15;
-  // B' for this lane: column 16 cb + li, k steps 0..KS-1
-  float bv[CB][KS];
-#pragma unroll
-  for (int cb = 0; cb < CB; ++cb) {
-    const int jj = 16 * cb + li, n = jj >> 1, q = jj & 1;
-#pragma unroll
-    for (int j = 0; j < KG; ++j) {
-      const float2 b = sB[n * K + g * KG + j];
-      bv[cb][2 * j] = q ? b.y : b.x;         // real part of a: (Br, Bi)
-      bv[cb][2 * j + 1] = q ? b.x : -b.y;    // imaginary part of a: (-Bi, Br)
-    }
-  }
+  // B' was staged as [cb][k step][lane] (see the staging in k_chain)
+  const float* bw = sBf + lane;
   int32_t ks[NK];
 #pragma unroll
   for (int t = 0; t < NK; ++t) ks[t] = S.kslot[t];
@@ -212,13 +206,25 @@ __device__ __forceinline__ void chain_rows_mfma(karg_step& S, float2* buf, const
     out_lo[r] = o;
   }
   const uint32_t blocks = 1u << (S.nrow - 4);
-  float* fb = reinterpret_cast<float*>(buf);
+  // Byte offsets in LDS.  A position is the OR of disjoint bit groups and
+  // the swizzle is XOR-linear, so swz(hi | c) = swz(hi) ^ swz(c): the lane's
+  // parts are swizzled once per step, the block's part once per block, and
+  // an address is one XOR (times 8 bytes; bit 2 carries the real / imaginary
+  // half of an output value, which the block part never has).
+  char* lb = reinterpret_cast<char*>(buf);
   const int q = li & 1;
+  int32_t ra[KG], wr[4], wn[CB];
+#pragma unroll
+  for (int j = 0; j < KG; ++j) ra[j] = 8 * chain_swz(in_lo | koff[j]);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) wr[r] = 8 * chain_swz(out_lo[r]) + 4 * q;
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb) wn[cb] = 8 * chain_swz(noff[cb]);
   for (uint32_t rb = wave; rb < blocks; rb += 4) {
-    const int32_t hi = rhi[rb];
+    const int32_t h8 = 8 * chain_swz(rhi[rb]);
     float2 a[KG];
 #pragma unroll
-    for (int j = 0; j < KG; ++j) a[j] = buf[chain_swz(hi | in_lo | koff[j])];
+    for (int j = 0; j < KG; ++j) a[j] = *reinterpret_cast<const float2*>(lb + (h8 ^ ra[j]));
     floatx4 acc[CB];
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) acc[cb] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -227,21 +233,23 @@ __device__ __forceinline__ void chain_rows_mfma(karg_step& S, float2* buf, const
       const float av = (s2 & 1) ? a[s2 >> 1].y : a[s2 >> 1].x;
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb)
-        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[cb][s2], acc[cb], 0, 0, 0);
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bw[(cb * KS + s2) * 64], acc[cb], 0, 0,
+                                                       0);
     }
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) fb[2 * chain_swz(hi | out_lo[r] | noff[cb]) + q] = acc[cb][r];
+      for (int r = 0; r < 4; ++r)
+        *reinterpret_cast<float*>(lb + (h8 ^ wn[cb] ^ wr[r])) = acc[cb][r];
   }
 }
 
-__device__ __forceinline__ void chain_step(karg_step& S, float2* buf, const float2* sB,
+__device__ __forceinline__ void chain_step(karg_step& S, float2* buf, const float* sBf,
                                            const int32_t* rhi) {
   if (S.mfma) {
 #define TNK_CHAIN_MFMA(A, B)                   \
   if (S.nk == A && S.nn == B) {                \
-    chain_rows_mfma<A, B>(S, buf, sB, rhi);    \
+    chain_rows_mfma<A, B>(S, buf, sBf, rhi);   \
     return;                                    \
   }
     TNK_CHAIN_MFMA(2, 3) TNK_CHAIN_MFMA(2, 4) TNK_CHAIN_MFMA(2, 5)
@@ -251,6 +259,7 @@ __device__ __forceinline__ void chain_step(karg_step& S, float2* buf, const floa
     TNK_CHAIN_MFMA(6, 3)
 #undef TNK_CHAIN_MFMA
   }
+  const float2* sB = reinterpret_cast<const float2*>(sBf);
   // the per-step stream kernel covers nk, nn in 0..4; so does the chain
 #define TNK_CHAIN_CASE(A, B)                \
   if (S.nk == A && S.nn == B) {             \
@@ -264,13 +273,32 @@ __device__ __forceinline__ void chain_step(karg_step& S, float2* buf, const floa
 #undef TNK_CHAIN_CASE
 }
 
+// Stage the small operand of a matrix-core step as B' in the lanes' read
+// order: float i is lane i % 64, k step (i / 64) % KS, column block
+// i / (64 KS); lane (g, li) holds real column 16 cb + li (complex n, part q)
+// and real k row s of lane group g (complex k = g K/4 + s/2, part p).
+__device__ __forceinline__ void chain_stage_mfma(karg_step& S, const float2* B, float* dst) {
+  const int nk = S.nk, nn = S.nn, K = 1 << nk;
+  const int KG = K / 4, KS = K / 2;
+  const int cnt = 4 << (nk + nn);
+  for (int i = threadIdx.x; i < cnt; i += 256) {
+    const int lane = i & 63, s2 = (i >> 6) % KS, cb = (i >> 6) / KS;
+    const int g = lane >> 4, li = lane & 15;
+    const int jj = 16 * cb + li, n = jj >> 1, q = jj & 1;
+    const int k = g * KG + (s2 >> 1), p = s2 & 1;
+    const float2 b = B[chain_off(k, S.kB, 0, nk) + chain_off(n, S.nB, 0, nn)];
+    dst[i] = p ? (q ? b.x : -b.y) : (q ? b.y : b.x);
+  }
+}
+
 template <int TB>
-__global__ void __launch_bounds__(256) k_chain(ChainArgs) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+k_chain(ChainArgs) {
   using Tab = ChainTables<TB>;
   constexpr int E = Tab::E;                        // tile elements per thread, at most
   constexpr int EB = E < 8 ? E : 8;                // loads in flight per batch
   __shared__ float2 buf[1 << TB];
-  __shared__ float2 sB[kChainB];
+  __shared__ __attribute__((aligned(16))) float sBf[kChainBF];
   __shared__ Tab tab;
   karg_chain& g = *(karg_chain*)__builtin_amdgcn_kernarg_segment_ptr();
   const int tid = threadIdx.x;
@@ -280,19 +308,18 @@ __global__ void __launch_bounds__(256) k_chain(ChainArgs) {
     const uint32_t e = (uint32_t)tid << 8;
     tab.ein[tid] = chain_off(e, g.in_log2, 8, tin);
     tab.eout[tid] = chain_off(e, g.out_log2, 8, tout);
-    tab.lin[tid] = chain_slot(e, g.in_slot, 8, tin);
-    tab.lout[tid] = chain_slot(e, g.out_slot, 8, tout);
+    tab.lin[tid] = 8 * chain_swz(chain_slot(e, g.in_slot, 8, tin));
+    tab.lout[tid] = 8 * chain_swz(chain_slot(e, g.out_slot, 8, tout));
   }
   {
-    int off = 0;
     for (int q = 0; q < nsteps; ++q) {
       karg_step& S = g.st[q];
       const int nk = S.nk, nn = S.nn, cnt = 1 << (nk + nn);
-      for (int i = tid; i < cnt; i += 256) {
-        const int n = i >> nk, k = i & ((1 << nk) - 1);
-        tab.boff[off + i] = (int32_t)(chain_off(k, S.kB, 0, nk) + chain_off(n, S.nB, 0, nn));
-      }
-      off += cnt;
+      if (!S.mfma)
+        for (int i = tid; i < cnt; i += 256) {
+          const int n = i >> nk, k = i & ((1 << nk) - 1);
+          tab.boff[S.voff0 + i] = (int32_t)(chain_off(k, S.kB, 0, nk) + chain_off(n, S.nB, 0, nn));
+        }
       // high row parts: per 256-row group (vector steps) or 16-row block
       const int lo = S.mfma ? 4 : 8;
       const int nhi = S.nrow > lo ? 1 << (S.nrow - lo) : 1;
@@ -306,9 +333,10 @@ __global__ void __launch_bounds__(256) k_chain(ChainArgs) {
   const int64_t by_lo = chain_off(blockIdx.x, g.pas_out, 0, lg < npas ? lg : npas);
   const int lo_in = tin < 8 ? tin : 8, lo_out = tout < 8 ? tout : 8;
   const int64_t xin_lo = chain_off(tid, g.in_log2, 0, lo_in);
-  const int32_t lin_lo = chain_slot(tid, g.in_slot, 0, lo_in);
+  const int32_t lin8 = 8 * chain_swz(chain_slot(tid, g.in_slot, 0, lo_in));
   const int64_t yout_lo = chain_off(tid, g.out_log2, 0, lo_out);
-  const int32_t lout_lo = chain_slot(tid, g.out_slot, 0, lo_out);
+  const int32_t lout8 = 8 * chain_swz(chain_slot(tid, g.out_slot, 0, lo_out));
+  char* lb = reinterpret_cast<char*>(buf);
   const uint32_t n_in = 1u << tin, n_out = 1u << tout;
   const uint64_t n_tiles = 1ull << npas;
   __syncthreads();
@@ -316,18 +344,21 @@ __global__ void __launch_bounds__(256) k_chain(ChainArgs) {
   for (uint64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
     const int64_t bx = bx_lo + chain_off(t, g.pas_in, lg, npas);
     const int64_t by = by_lo + chain_off(t, g.pas_out, lg, npas);
-    // small operands, [n][k] per step
+    // small operands: [n][k] complex (vector steps) or B' (matrix steps)
     if (!staged || g.b_per_tile) {
-      int off = 0;
       for (int q = 0; q < nsteps; ++q) {
         karg_step& S = g.st[q];
-        const int cnt = 1 << (S.nk + S.nn);
         int64_t bb = 0;
 #pragma unroll 1
         for (int j = 0; j < S.nbb; ++j) bb += (int64_t)((t >> S.bpas[j]) & 1ull) << S.bB[j];
         const float2* B = S.B + bb;
-        for (int i = tid; i < cnt; i += 256) sB[off + i] = B[tab.boff[off + i]];
-        off += cnt;
+        if (S.mfma) {
+          chain_stage_mfma(S, B, sBf + S.boff0);
+        } else {
+          const int cnt = 1 << (S.nk + S.nn);
+          float2* dst = reinterpret_cast<float2*>(sBf + S.boff0);
+          for (int i = tid; i < cnt; i += 256) dst[i] = B[tab.boff[S.voff0 + i]];
+        }
       }
       staged = true;
     }
@@ -340,14 +371,13 @@ __global__ void __launch_bounds__(256) k_chain(ChainArgs) {
         if ((uint32_t)((e0 + e) << 8) + tid < n_in) v[e] = g.X[bx + xin_lo + tab.ein[e0 + e]];
 #pragma unroll
       for (int e = 0; e < EB; ++e)
-        if ((uint32_t)((e0 + e) << 8) + tid < n_in) buf[chain_swz(lin_lo | tab.lin[e0 + e])] = v[e];
+        if ((uint32_t)((e0 + e) << 8) + tid < n_in)
+          *reinterpret_cast<float2*>(lb + (lin8 ^ tab.lin[e0 + e])) = v[e];
     }
     __syncthreads();
-    int off = 0;
     for (int q = 0; q < nsteps; ++q) {
       karg_step& S = g.st[q];
-      chain_step(S, buf, sB + off, tab.rhi[q]);
-      off += 1 << (S.nk + S.nn);
+      chain_step(S, buf, sBf + S.boff0, tab.rhi[q]);
       __syncthreads();
     }
     // store the output tile
@@ -356,7 +386,8 @@ __global__ void __launch_bounds__(256) k_chain(ChainArgs) {
       float2 v[EB];
 #pragma unroll
       for (int e = 0; e < EB; ++e)
-        if ((uint32_t)((e0 + e) << 8) + tid < n_out) v[e] = buf[chain_swz(lout_lo | tab.lout[e0 + e])];
+        if ((uint32_t)((e0 + e) << 8) + tid < n_out)
+          v[e] = *reinterpret_cast<const float2*>(lb + (lout8 ^ tab.lout[e0 + e]));
 #pragma unroll
       for (int e = 0; e < EB; ++e)
         if ((uint32_t)((e0 + e) << 8) + tid < n_out) g.Y[by + yout_lo + tab.eout[e0 + e]] = v[e];

@@ -109,10 +109,6 @@ struct StepBits {  // global bit ids of a step's classes, in stride-array order
   Bits batch, M, N, K;
 };
 
-// Chain steps the matrix-core path covers (see kernels_chain.h).
-bool chain_mfma_shape(int nk, int nn) {
-  return nk >= 2 && nk <= 6 && nn >= 3 && nn <= 5 && nk + nn <= 9;
-}
 
 // Tile of a chain candidate first..last (see ChainGroup); returns false when
 // it does not fit the LDS tile or a summed / batch bit is misplaced.
@@ -131,11 +127,6 @@ bool build_chain(const Plan& p, const std::vector<Layout>& lay, const std::vecto
     std::sort(N.begin(), N.end());
     created = unite(created, N);
   }
-  // small operands of all steps are staged together
-  int64_t b_elems = 0;
-  for (int k = first; k <= last; ++k)
-    b_elems += (int64_t)1 << (sb[k].K.size() + sb[k].N.size());
-  if (b_elems > kChainBElems) return false;
   // batch bits must stay outside the tile; simulate the live tile bits
   Bits live = in_act;
   int max_live = (int)live.size();
@@ -219,6 +210,7 @@ bool build_chain(const Plan& p, const std::vector<Layout>& lay, const std::vecto
   g.last = last;
   g.phase = p.steps[first].phase;
   Bits tile_live = unite(in_act, ptile);
+  int64_t staged_f = 0, staged_v = 0;
   for (int k = first; k <= last; ++k) {
     const StepDesc& S = p.steps[k];
     ChainStepDesc d;
@@ -236,8 +228,14 @@ bool build_chain(const Plan& p, const std::vector<Layout>& lay, const std::vecto
     std::sort(rs.begin(), rs.end());
     d.rslot = rs;
     d.nrow = (int32_t)rs.size();
-    // shapes only the matrix-core step runs need 16-row blocks
-    if ((sb[k].K.size() > 4 || sb[k].N.size() > 4) && d.nrow < 4) return false;
+    // shapes only the matrix-core step runs need 16-row blocks; the small
+    // operands of all steps are staged together
+    const int nk = (int)sb[k].K.size(), nn = (int)sb[k].N.size();
+    const bool on_mfma = chain_step_mfma(nk, nn, d.nrow, p.flags);
+    if ((nk > 4 || nn > 4) && !on_mfma) return false;
+    staged_f += (on_mfma ? 4 : 2) << (nk + nn);
+    if (!on_mfma) staged_v += 1 << (nk + nn);
+    if (staged_f > kChainBFloats || staged_v > kChainVElems) return false;
     d.kB = S.kB;
     d.nB = S.nB;
     d.bB = S.bB;
@@ -481,9 +479,8 @@ static void schedule_pass(Plan& p) {
   p.chains.clear();
   if (!(p.flags & 8u)) {
     // vector-unit chain steps: 2^nk, 2^nn <= 16 (the stream kernel's
-    // shapes); matrix-core chain steps also take GEMM-kind steps with
-    // 4 <= 2^nk <= 64, 8 <= 2^nn <= 32 and a small operand of at most 2^9
-    // entries (register budget of the kernel)
+    // shapes); matrix-core chain steps also take GEMM-kind steps with a
+    // small operand (chain_mfma_shape)
     const bool mfma = !(p.flags & 32u);
     auto fusable = [&](int k) {
       const StepDesc& S = p.steps[k];

@@ -58,7 +58,24 @@ constexpr int64_t kCtrStride = 32;       // int32 slots between completion count
 constexpr int kChainMaxSteps = 8;
 constexpr int kChainTileBits = 12;   // LDS tile: 2^12 complex64 per buffer
 constexpr int kChainPassive = 40;    // bits enumerating tiles
-constexpr int kChainBElems = 1024;   // small operands staged in LDS, all steps
+constexpr int kChainBFloats = 4096;  // staged small operands in LDS, all steps (floats)
+constexpr int kChainVElems = 512;    // of which complex entries of vector-unit steps
+
+// Which chain steps run on the matrix cores: 4 <= 2^nk <= 64 summed and
+// 8 <= 2^nn <= 32 new values with 2^(nk+nn) <= 512, at least 16 rows, and
+// matrix cores not switched off (TN_FLAG_CHAIN_VALU).  Such a step stages
+// the real embedding of its small operand (4 floats per complex entry); a
+// vector-unit step stages the complex entries (2 floats each).  (Wider small
+// operands, 2^(nk+nn) = 1024, were measured slower inside chains than as
+// stand-alone GEMM launches: the larger staging area and register budget
+// halve the chain kernel's occupancy.)
+inline bool chain_mfma_shape(int nk, int nn) {
+  return nk >= 2 && nk <= 6 && nn >= 3 && nn <= 5 && nk + nn <= 9;
+}
+inline bool chain_step_mfma(int nk, int nn, int nrow, uint32_t flags) {
+  return !(flags & 32u) && chain_mfma_shape(nk, nn) && nrow >= 4;
+}
+
 
 struct ChainStepDesc {
   int32_t step;                      // step index

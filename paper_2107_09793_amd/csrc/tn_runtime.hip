@@ -296,7 +296,8 @@ tn_status run_chain(const Ctx& c, const tn::ChainGroup& g, uint64_t outer_val,
   const tn::Plan& p = c.p;
   static_assert(sizeof(tnk::ChainArgs) % 4 == 0, "argument copy in 32-bit words");
   static_assert(tnk::kChainSteps == tn::kChainMaxSteps && tnk::kChainTile == tn::kChainTileBits &&
-                    tnk::kChainPas == tn::kChainPassive && tnk::kChainB == tn::kChainBElems,
+                    tnk::kChainPas == tn::kChainPassive && tnk::kChainBF == tn::kChainBFloats &&
+                    tnk::kChainV == tn::kChainVElems,
                 "chain limits agree");
   tnk::ChainArgs a;
   memset(&a, 0, sizeof a);
@@ -320,11 +321,11 @@ tn_status run_chain(const Ctx& c, const tn::ChainGroup& g, uint64_t outer_val,
     a.pas_in[i] = g.pas_in[i];
     a.pas_out[i] = g.pas_out[i];
   }
-  int total = 0;
+  int fl = 0, ve = 0;   // staged floats, vector-step table entries
   for (size_t q = 0; q < g.st.size(); ++q) {
     const tn::ChainStepDesc& d = g.st[q];
     tnk::ChainStepArgs& t = a.st[q];
-    if (d.kslot.size() > 6 || d.nslot.size() > 5 || d.rslot.size() > (size_t)tnk::kChainTile ||
+    if (d.kslot.size() > 6 || d.nslot.size() > 6 || d.rslot.size() > (size_t)tnk::kChainTile ||
         d.bB.size() > (size_t)tnk::kChainTile)
       return fail(TN_E_INVALID, "chain step exceeds its descriptor");
     t.B = node_ptr(c, p.steps[d.step].b, outer_val);
@@ -346,23 +347,24 @@ tn_status run_chain(const Ctx& c, const tn::ChainGroup& g, uint64_t outer_val,
       t.bpas[j] = d.bpas[j];
     }
     if (!d.bB.empty()) a.b_per_tile = 1;
-    // the matrix-core step covers 2 <= nk <= 6, 3 <= nn <= 5, nk + nn <= 9
-    const bool mshape = t.nk >= 2 && t.nk <= 6 && t.nn >= 3 && t.nn <= 5 && t.nk + t.nn <= 9;
-    t.mfma = !(p.flags & 32u) && mshape && t.nrow >= 4;
+    t.boff0 = fl;
+    t.voff0 = ve;
+    t.mfma = tn::chain_step_mfma(t.nk, t.nn, t.nrow, p.flags);
     if ((t.nk > 4 || t.nn > 4) && !t.mfma)
       return fail(TN_E_INVALID, "chain step shape needs the matrix-core path");
     if (t.mfma ? t.nrow > 10 : t.nrow > 14)   // row-part table: 64 entries per step
       return fail(TN_E_INVALID, "chain step has more rows than its table");
-    total += 1 << (t.nk + t.nn);
+    fl += (t.mfma ? 4 : 2) << (t.nk + t.nn);
+    if (!t.mfma) ve += 1 << (t.nk + t.nn);
   }
-  a.b_total = total;
-  if (total > tnk::kChainB || g.tile_bits > tnk::kChainTile)
+  a.b_total = fl;
+  if (fl > tnk::kChainBF || ve > tnk::kChainV || g.tile_bits > tnk::kChainTile)
     return fail(TN_E_INVALID, "chain exceeds its on-chip limits");
   const uint64_t n_tiles = 1ull << a.npas;
   const unsigned grid = (unsigned)std::min<uint64_t>(n_tiles, 1u << 16);
   bool timed = false;
   static_assert(sizeof(a.st[0].kslot) / sizeof(a.st[0].kslot[0]) >= 6 &&
-                    sizeof(a.st[0].nslot) / sizeof(a.st[0].nslot[0]) >= 5,
+                    sizeof(a.st[0].nslot) / sizeof(a.st[0].nslot[0]) >= 6,
                 "chain step arrays hold the largest summed / new bit counts");
   if (probe && !probe->done)
     for (int k = g.first; k <= g.last; ++k) timed |= probe->step == k;
