@@ -50,7 +50,8 @@ struct ChainArgs {
   float2* Y;         // chain output (result of the last step)
   int32_t nsteps, tin, tout, npas;
   int32_t b_per_tile;   // some small operand depends on passive (batch) bits
-  int32_t b_total;      // staged small-operand elements (sum of 2^(nk+nn))
+  int32_t b_total;      // staged small-operand floats
+  int32_t split;        // matrix-core steps in split-BF16 (three BF16 products)
   int32_t in_slot[kChainTile], in_log2[kChainTile];    // input tile bits, input-stride order
   int32_t out_slot[kChainTile], out_log2[kChainTile];  // output tile bits, output-stride order
   int32_t pas_in[kChainPas], pas_out[kChainPas];       // passive bits: X / Y strides
@@ -244,8 +245,131 @@ __device__ __forceinline__ void chain_rows_mfma(karg_step& S, float2* buf, const
   }
 }
 
+// Split-BF16 variant (v_mfma_f32_16x16x16_bf16): each real value x is
+// hi + lo with hi = bf16(x), lo = bf16(x - hi) (round to nearest even), and
+// the product is hi*hi + hi*lo + lo*hi with float32 accumulation.  A k step
+// covers 16 real k: lane group g supplies real k 4g .. 4g+3, i.e. complex
+// k = 8 s + 2 g and 8 s + 2 g + 1 (zero beyond K when K = 4).  B' hi and lo
+// are staged as 4 BF16 per lane, in the lanes' read order.
+typedef short shortx4 __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 b4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void chain_split4(f4v v, shortx4& hi, shortx4& lo) {
+  const b4v h = __builtin_convertvector(v, b4v);
+  const f4v hf = __builtin_convertvector(h, f4v);
+  const b4v l = __builtin_convertvector(v - hf, b4v);
+  hi = __builtin_bit_cast(shortx4, h);
+  lo = __builtin_bit_cast(shortx4, l);
+}
+
+template <int NK, int NN>
+__device__ __forceinline__ void chain_rows_mfma_sb(karg_step& S, float2* buf, const float* sBf,
+                                                   const int32_t* rhi) {
+  constexpr int K = 1 << NK, N = 1 << NN;
+  constexpr int KS = K >= 8 ? K / 8 : 1;   // k steps of 16 real values
+  constexpr int CB = N / 8;                // 16-column blocks of the real output
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  const shortx4* bh = reinterpret_cast<const shortx4*>(sBf) + lane;
+  const shortx4* bl = bh + CB * KS * 64;
+  int32_t ks[NK];
+#pragma unroll
+  for (int t = 0; t < NK; ++t) ks[t] = S.kslot[t];
+  // complex k of the lane: 8 s + 2 g + e, e = 0, 1
+  int32_t koff[KS][2];
+  bool kok[KS][2];
+#pragma unroll
+  for (int s2 = 0; s2 < KS; ++s2)
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int k = 8 * s2 + 2 * g + e;
+      int32_t o = 0;
+#pragma unroll
+      for (int t = 0; t < NK; ++t) o |= ((k >> t) & 1) << ks[t];
+      koff[s2][e] = o;
+      kok[s2][e] = k < K;
+    }
+  int32_t noff[CB];
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb) {
+    const int n = (16 * cb + li) >> 1;
+    int32_t o = 0;
+#pragma unroll
+    for (int t = 0; t < NN; ++t) o |= ((n >> t) & 1) << S.nslot[t];
+    noff[cb] = o;
+  }
+  int32_t rs[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) rs[t] = S.rslot[t];
+  int32_t in_lo = 0;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) in_lo |= ((li >> t) & 1) << rs[t];
+  int32_t wr[4], wn[CB];
+  const int q = li & 1;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    int32_t o = 0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) o |= (((4 * g + r) >> t) & 1) << rs[t];
+    wr[r] = 8 * chain_swz(o) + 4 * q;
+  }
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb) wn[cb] = 8 * chain_swz(noff[cb]);
+  int32_t ra[KS][2];
+#pragma unroll
+  for (int s2 = 0; s2 < KS; ++s2)
+#pragma unroll
+    for (int e = 0; e < 2; ++e) ra[s2][e] = 8 * chain_swz(in_lo | koff[s2][e]);
+  char* lb = reinterpret_cast<char*>(buf);
+  const uint32_t blocks = 1u << (S.nrow - 4);
+  for (uint32_t rb = wave; rb < blocks; rb += 4) {
+    const int32_t h8 = 8 * chain_swz(rhi[rb]);
+    shortx4 ah[KS], al[KS];
+#pragma unroll
+    for (int s2 = 0; s2 < KS; ++s2) {
+      float2 a0 = kok[s2][0] ? *reinterpret_cast<const float2*>(lb + (h8 ^ ra[s2][0]))
+                             : make_float2(0.f, 0.f);
+      float2 a1 = kok[s2][1] ? *reinterpret_cast<const float2*>(lb + (h8 ^ ra[s2][1]))
+                             : make_float2(0.f, 0.f);
+      const f4v v = {a0.x, a0.y, a1.x, a1.y};
+      chain_split4(v, ah[s2], al[s2]);
+    }
+    floatx4 acc[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) acc[cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s2 = 0; s2 < KS; ++s2)
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        const shortx4 vh = bh[(cb * KS + s2) * 64], vl = bl[(cb * KS + s2) * 64];
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[s2], vh, acc[cb], 0, 0, 0);
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[s2], vl, acc[cb], 0, 0, 0);
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[s2], vh, acc[cb], 0, 0, 0);
+      }
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        *reinterpret_cast<float*>(lb + (h8 ^ wn[cb] ^ wr[r])) = acc[cb][r];
+  }
+}
+
 __device__ __forceinline__ void chain_step(karg_step& S, float2* buf, const float* sBf,
-                                           const int32_t* rhi) {
+                                           const int32_t* rhi, bool split) {
+  if (S.mfma && split) {
+#define TNK_CHAIN_MFMA(A, B)                      \
+  if (S.nk == A && S.nn == B) {                   \
+    chain_rows_mfma_sb<A, B>(S, buf, sBf, rhi);   \
+    return;                                       \
+  }
+    TNK_CHAIN_MFMA(2, 3) TNK_CHAIN_MFMA(2, 4) TNK_CHAIN_MFMA(2, 5)
+    TNK_CHAIN_MFMA(3, 3) TNK_CHAIN_MFMA(3, 4) TNK_CHAIN_MFMA(3, 5)
+    TNK_CHAIN_MFMA(4, 3) TNK_CHAIN_MFMA(4, 4) TNK_CHAIN_MFMA(4, 5)
+    TNK_CHAIN_MFMA(5, 3) TNK_CHAIN_MFMA(5, 4)
+    TNK_CHAIN_MFMA(6, 3)
+#undef TNK_CHAIN_MFMA
+  }
   if (S.mfma) {
 #define TNK_CHAIN_MFMA(A, B)                   \
   if (S.nk == A && S.nn == B) {                \
@@ -271,6 +395,36 @@ __device__ __forceinline__ void chain_step(karg_step& S, float2* buf, const floa
   TNK_CHAIN_ROW(0) TNK_CHAIN_ROW(1) TNK_CHAIN_ROW(2) TNK_CHAIN_ROW(3) TNK_CHAIN_ROW(4)
 #undef TNK_CHAIN_ROW
 #undef TNK_CHAIN_CASE
+}
+
+// Split-BF16 staging: entry i (lane i % 64, k step (i / 64) % KS, column
+// block i / (64 KS)) holds the lane's 4 real k of B' as BF16 hi, and the
+// same index past CB KS 64 entries as BF16 lo.
+__device__ __forceinline__ void chain_stage_mfma_sb(karg_step& S, const float2* B, float* dst) {
+  const int nk = S.nk, nn = S.nn, K = 1 << nk;
+  const int KS = K >= 8 ? K / 8 : 1, CB = (1 << nn) / 8;
+  const int cnt = CB * KS * 64;
+  shortx4* dh = reinterpret_cast<shortx4*>(dst);
+  shortx4* dl = dh + cnt;
+  for (int i = threadIdx.x; i < cnt; i += 256) {
+    const int lane = i & 63, s2 = (i >> 6) % KS, cb = (i >> 6) / KS;
+    const int g = lane >> 4, li = lane & 15;
+    const int jj = 16 * cb + li, n = jj >> 1, q = jj & 1;
+    float v[4];
+    for (int j = 0; j < 4; ++j) {
+      const int kr = 16 * s2 + 4 * g + j, k = kr >> 1, p = kr & 1;
+      float x = 0.f;
+      if (k < K) {
+        const float2 b = B[chain_off(k, S.kB, 0, nk) + chain_off(n, S.nB, 0, nn)];
+        x = p ? (q ? b.x : -b.y) : (q ? b.y : b.x);
+      }
+      v[j] = x;
+    }
+    shortx4 h, l;
+    chain_split4(f4v{v[0], v[1], v[2], v[3]}, h, l);
+    dh[i] = h;
+    dl[i] = l;
+  }
 }
 
 // Stage the small operand of a matrix-core step as B' in the lanes' read
@@ -352,7 +506,9 @@ k_chain(ChainArgs) {
 #pragma unroll 1
         for (int j = 0; j < S.nbb; ++j) bb += (int64_t)((t >> S.bpas[j]) & 1ull) << S.bB[j];
         const float2* B = S.B + bb;
-        if (S.mfma) {
+        if (S.mfma && g.split) {
+          chain_stage_mfma_sb(S, B, sBf + S.boff0);
+        } else if (S.mfma) {
           chain_stage_mfma(S, B, sBf + S.boff0);
         } else {
           const int cnt = 1 << (S.nk + S.nn);
@@ -377,7 +533,7 @@ k_chain(ChainArgs) {
     __syncthreads();
     for (int q = 0; q < nsteps; ++q) {
       karg_step& S = g.st[q];
-      chain_step(S, buf, sBf + S.boff0, tab.rhi[q]);
+      chain_step(S, buf, sBf + S.boff0, tab.rhi[q], g.split != 0);
       __syncthreads();
     }
     // store the output tile

@@ -233,7 +233,7 @@ bool build_chain(const Plan& p, const std::vector<Layout>& lay, const std::vecto
     const int nk = (int)sb[k].K.size(), nn = (int)sb[k].N.size();
     const bool on_mfma = chain_step_mfma(nk, nn, d.nrow, p.flags);
     if ((nk > 4 || nn > 4) && !on_mfma) return false;
-    staged_f += (on_mfma ? 4 : 2) << (nk + nn);
+    staged_f += chain_staged_floats(nk, nn, on_mfma);
     if (!on_mfma) staged_v += 1 << (nk + nn);
     if (staged_f > kChainBFloats || staged_v > kChainVElems) return false;
     d.kB = S.kB;

@@ -75,6 +75,11 @@ inline bool chain_mfma_shape(int nk, int nn) {
 inline bool chain_step_mfma(int nk, int nn, int nrow, uint32_t flags) {
   return !(flags & 32u) && chain_mfma_shape(nk, nn) && nrow >= 4;
 }
+// Floats a chain step stages: the complex entries (vector units), or B' in
+// the lanes' order, padded to 8 complex k (split-BF16 k steps cover 16 reals).
+inline int chain_staged_floats(int nk, int nn, bool mfma) {
+  return mfma ? 4 * (nk < 3 ? 8 : 1 << nk) << nn : 2 << (nk + nn);
+}
 
 
 struct ChainStepDesc {

@@ -354,10 +354,11 @@ tn_status run_chain(const Ctx& c, const tn::ChainGroup& g, uint64_t outer_val,
       return fail(TN_E_INVALID, "chain step shape needs the matrix-core path");
     if (t.mfma ? t.nrow > 10 : t.nrow > 14)   // row-part table: 64 entries per step
       return fail(TN_E_INVALID, "chain step has more rows than its table");
-    fl += (t.mfma ? 4 : 2) << (t.nk + t.nn);
+    fl += tn::chain_staged_floats(t.nk, t.nn, t.mfma);
     if (!t.mfma) ve += 1 << (t.nk + t.nn);
   }
   a.b_total = fl;
+  a.split = p.precision == tn::PREC_SPLIT_BF16;
   if (fl > tnk::kChainBF || ve > tnk::kChainV || g.tile_bits > tnk::kChainTile)
     return fail(TN_E_INVALID, "chain exceeds its on-chip limits");
   const uint64_t n_tiles = 1ull << a.npas;

@@ -75,3 +75,31 @@ def test_chain_sliced_workload_bitwise():
     c = mfma.contract(leaves, per_slice=True).cpu().numpy()
     rms = np.sqrt(np.mean(np.abs(b) ** 2))
     assert np.max(np.abs(c - b)) <= 1e-5 * rms
+    del mfma
+    torch.cuda.empty_cache()
+    # split-BF16 (its matrix-core chain steps include shapes 4x3 and 4x5)
+    sb = Plan.from_network(w.tn, w.path, w.sliced, precision="split_bf16")
+    d = sb.contract(leaves, per_slice=True).cpu().numpy()
+    assert np.max(np.abs(d - b)) <= 1e-3 * rms
+
+
+@pytest.mark.parametrize("cfg", [(3, 4, 4, 12, 16, 2), (7, 4, 4, 14, 32, 2), (9, 4, 4, 10, 16, 3),
+                                 (7, 4, 5, 14, 32, 2)])
+def test_chain_split_bf16(cfg):
+    """Split-BF16 matrix-core chain steps (three BF16 products, float32
+    accumulation) against the complex128 oracle at 1e-3 of the rms slice
+    value, and against the vector-unit chain of the same plan."""
+    from paper_2107_09793_amd import Plan
+    dev = _dev()
+    tn, p, sl = _batch_net(*cfg)
+    leaves = [torch.from_numpy(t.astype(np.complex64)).to(dev) for t in tn.tensors]
+    sb = Plan.from_network(tn, p, sl, precision="split_bf16")
+    assert sb.info()["n_chains"] > 0
+    assert any(2 <= len(d["kslot"]) <= 6 and 3 <= len(d["nslot"]) <= 5
+               and len(d["kslot"]) + len(d["nslot"]) <= 9 and d["nrow"] >= 4
+               for ch in sb.chains() for d in ch["st"])
+    got = sb.contract(leaves, per_slice=True).cpu().numpy()
+    ref = tn_oracle.contract(tn.tensors, tn.labels, tn.dims, tn.open, p, sl, per_slice=True)
+    ref = np.asarray(ref).reshape(got.shape)
+    rms = np.sqrt(np.mean(np.abs(ref) ** 2))
+    assert np.max(np.abs(got - ref)) <= 1e-3 * rms

@@ -189,12 +189,14 @@ def test_cpu_execution_of_fused_chains_matches_oracle(cfg):
         assert 2 <= len(ch["st"]) <= 8 and ch["tile_bits"] <= 12
         for k in range(ch["first"], ch["last"]):
             assert steps[k + 1]["a"] == pl.n_tensors + k and steps[k]["c_offset"] == -1
-        # staged small operands: 4 floats per entry on the matrix cores, 2 on
-        # the vector units, 4096 floats in all
-        def mf(d):
+        # staged small operands: 4 floats per entry on the matrix cores (k
+        # padded to 8 complex values), 2 on the vector units, 4096 floats in all
+        def staged(d):
             nk, nn = len(d["kslot"]), len(d["nslot"])
-            return 2 <= nk <= 6 and 3 <= nn <= 5 and nk + nn <= 9 and d["nrow"] >= 4
-        used = sum((4 if mf(d) else 2) * 2 ** (len(d["kslot"]) + len(d["nslot"])) for d in ch["st"])
+            if 2 <= nk <= 6 and 3 <= nn <= 5 and nk + nn <= 9 and d["nrow"] >= 4:
+                return 4 * max(2 ** nk, 8) * 2 ** nn
+            return 2 * 2 ** (nk + nn)
+        used = sum(staged(d) for d in ch["st"])
         assert used <= 4096
     got, _ = execute(pl, tn.tensors)
     ref = np.asarray(tn_oracle.contract(tn.tensors, tn.labels, tn.dims, tn.open, p, sl)).reshape(-1)
