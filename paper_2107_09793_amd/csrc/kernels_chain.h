@@ -152,12 +152,28 @@ __device__ __forceinline__ void chain_rows(karg_step& S, float2* buf, const floa
 // 16 rows at a time.  In k step s, lane group g = lane / 16 supplies complex
 // k = g K/4 + s/2, real part s % 2, so a lane reads its row's K/4 values
 // once; B' is staged in LDS in the order the lanes read it (one float per
-// lane and instruction, consecutive across lanes).  Output lane layout: rows
-// 4 (lane / 16) + r, real column lane % 16 of the 16-column block.  The
-// row's values are all read before any is written, and 16-row blocks of
+// lane and instruction, consecutive across lanes), and held in registers
+// for the whole step when it is small.  Output lane layout: rows
+// 4 (lane / 16) + r, real column lane % 16 of the 16-column block (which
+// column that is: chain_col).  The row's values are all read before any is written, and 16-row blocks of
 // different waves are disjoint, so the step runs in place.  Sums run in the
 // matrix core's order, not the stream kernel's.
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Real output column of lane li in 16-column block cb.  With two or more
+// blocks, blocks 2c and 2c + 1 hold the real and imaginary parts of complex
+// columns 16 c .. 16 c + 15, so a lane ends with both parts of one value and
+// writes it as one 8-byte store; a single block holds 8 complex columns with
+// real and imaginary parts in alternate lanes.
+__device__ __forceinline__ void chain_col(int cb, int li, int CB, int& n, int& q) {
+  if (CB >= 2) {
+    n = 16 * (cb >> 1) + li;
+    q = cb & 1;
+  } else {
+    n = li >> 1;
+    q = li & 1;
+  }
+}
 
 template <int NK, int NN>
 __device__ __forceinline__ void chain_rows_mfma(karg_step& S, float2* buf, const float* sBf,
@@ -182,14 +198,16 @@ __device__ __forceinline__ void chain_rows_mfma(karg_step& S, float2* buf, const
     for (int t = 0; t < NK; ++t) o |= ((k >> t) & 1) << ks[t];
     koff[j] = o;
   }
-  int32_t noff[CB];
+  constexpr int CP = CB >= 2 ? CB / 2 : 1;   // stores per output row
+  int32_t noff[CP];
 #pragma unroll
-  for (int cb = 0; cb < CB; ++cb) {
-    const int n = (16 * cb + li) >> 1;
+  for (int c = 0; c < CP; ++c) {
+    int n, qq;
+    chain_col(2 * c, li, CB, n, qq);
     int32_t o = 0;
 #pragma unroll
     for (int t = 0; t < NN; ++t) o |= ((n >> t) & 1) << S.nslot[t];
-    noff[cb] = o;
+    noff[c] = o;
   }
   // in-block row offsets: the lane's input row li, its output rows 4 g + r
   int32_t rs[4];
@@ -213,14 +231,22 @@ __device__ __forceinline__ void chain_rows_mfma(karg_step& S, float2* buf, const
   // an address is one XOR (times 8 bytes; bit 2 carries the real / imaginary
   // half of an output value, which the block part never has).
   char* lb = reinterpret_cast<char*>(buf);
-  const int q = li & 1;
-  int32_t ra[KG], wr[4], wn[CB];
+  const int q = CB >= 2 ? 0 : li & 1;
+  int32_t ra[KG], wr[4], wn[CP];
 #pragma unroll
   for (int j = 0; j < KG; ++j) ra[j] = 8 * chain_swz(in_lo | koff[j]);
 #pragma unroll
   for (int r = 0; r < 4; ++r) wr[r] = 8 * chain_swz(out_lo[r]) + 4 * q;
 #pragma unroll
-  for (int cb = 0; cb < CB; ++cb) wn[cb] = 8 * chain_swz(noff[cb]);
+  for (int c = 0; c < CP; ++c) wn[c] = 8 * chain_swz(noff[c]);
+  // B' is held in registers for the whole step when it is small, else read
+  // per block
+  constexpr bool BREG = KS * CB <= 16;
+  float bv[BREG ? KS * CB : 1];
+  if (BREG) {
+#pragma unroll
+    for (int i = 0; i < KS * CB; ++i) bv[i] = bw[i * 64];
+  }
   for (uint32_t rb = wave; rb < blocks; rb += 4) {
     const int32_t h8 = 8 * chain_swz(rhi[rb]);
     float2 a[KG];
@@ -234,14 +260,20 @@ __device__ __forceinline__ void chain_rows_mfma(karg_step& S, float2* buf, const
       const float av = (s2 & 1) ? a[s2 >> 1].y : a[s2 >> 1].x;
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb)
-        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bw[(cb * KS + s2) * 64], acc[cb], 0, 0,
-                                                       0);
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+            av, BREG ? bv[BREG ? cb * KS + s2 : 0] : bw[(cb * KS + s2) * 64], acc[cb], 0, 0, 0);
     }
+    if (CB >= 2) {
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb)
+      for (int c = 0; c < CP; ++c)
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        *reinterpret_cast<float*>(lb + (h8 ^ wn[cb] ^ wr[r])) = acc[cb][r];
+        for (int r = 0; r < 4; ++r)
+          *reinterpret_cast<float2*>(lb + (h8 ^ wn[c] ^ wr[r])) =
+              make_float2(acc[2 * c][r], acc[2 * c + 1][r]);
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) *reinterpret_cast<float*>(lb + (h8 ^ wn[0] ^ wr[r])) = acc[0][r];
+    }
   }
 }
 
@@ -290,14 +322,16 @@ __device__ __forceinline__ void chain_rows_mfma_sb(karg_step& S, float2* buf, co
       koff[s2][e] = o;
       kok[s2][e] = k < K;
     }
-  int32_t noff[CB];
+  constexpr int CP = CB >= 2 ? CB / 2 : 1;
+  int32_t noff[CP];
 #pragma unroll
-  for (int cb = 0; cb < CB; ++cb) {
-    const int n = (16 * cb + li) >> 1;
+  for (int c = 0; c < CP; ++c) {
+    int n, qq;
+    chain_col(2 * c, li, CB, n, qq);
     int32_t o = 0;
 #pragma unroll
     for (int t = 0; t < NN; ++t) o |= ((n >> t) & 1) << S.nslot[t];
-    noff[cb] = o;
+    noff[c] = o;
   }
   int32_t rs[4];
 #pragma unroll
@@ -305,8 +339,8 @@ __device__ __forceinline__ void chain_rows_mfma_sb(karg_step& S, float2* buf, co
   int32_t in_lo = 0;
 #pragma unroll
   for (int t = 0; t < 4; ++t) in_lo |= ((li >> t) & 1) << rs[t];
-  int32_t wr[4], wn[CB];
-  const int q = li & 1;
+  int32_t wr[4], wn[CP];
+  const int q = CB >= 2 ? 0 : li & 1;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     int32_t o = 0;
@@ -315,7 +349,7 @@ __device__ __forceinline__ void chain_rows_mfma_sb(karg_step& S, float2* buf, co
     wr[r] = 8 * chain_swz(o) + 4 * q;
   }
 #pragma unroll
-  for (int cb = 0; cb < CB; ++cb) wn[cb] = 8 * chain_swz(noff[cb]);
+  for (int c = 0; c < CP; ++c) wn[c] = 8 * chain_swz(noff[c]);
   int32_t ra[KS][2];
 #pragma unroll
   for (int s2 = 0; s2 < KS; ++s2)
@@ -323,6 +357,15 @@ __device__ __forceinline__ void chain_rows_mfma_sb(karg_step& S, float2* buf, co
     for (int e = 0; e < 2; ++e) ra[s2][e] = 8 * chain_swz(in_lo | koff[s2][e]);
   char* lb = reinterpret_cast<char*>(buf);
   const uint32_t blocks = 1u << (S.nrow - 4);
+  constexpr bool BREG = KS * CB <= 4;   // B' hi and lo in registers for the step
+  shortx4 rh[BREG ? KS * CB : 1], rl[BREG ? KS * CB : 1];
+  if (BREG) {
+#pragma unroll
+    for (int i = 0; i < KS * CB; ++i) {
+      rh[i] = bh[i * 64];
+      rl[i] = bl[i * 64];
+    }
+  }
   for (uint32_t rb = wave; rb < blocks; rb += 4) {
     const int32_t h8 = 8 * chain_swz(rhi[rb]);
     shortx4 ah[KS], al[KS];
@@ -342,19 +385,32 @@ __device__ __forceinline__ void chain_rows_mfma_sb(karg_step& S, float2* buf, co
     for (int s2 = 0; s2 < KS; ++s2)
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) {
-        const shortx4 vh = bh[(cb * KS + s2) * 64], vl = bl[(cb * KS + s2) * 64];
+        const int i = cb * KS + s2;
+        const shortx4 vh = BREG ? rh[BREG ? i : 0] : bh[i * 64];
+        const shortx4 vl = BREG ? rl[BREG ? i : 0] : bl[i * 64];
         acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[s2], vh, acc[cb], 0, 0, 0);
         acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[s2], vl, acc[cb], 0, 0, 0);
         acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[s2], vh, acc[cb], 0, 0, 0);
       }
+    if (CB >= 2) {
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb)
+      for (int c = 0; c < CP; ++c)
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        *reinterpret_cast<float*>(lb + (h8 ^ wn[cb] ^ wr[r])) = acc[cb][r];
+        for (int r = 0; r < 4; ++r)
+          *reinterpret_cast<float2*>(lb + (h8 ^ wn[c] ^ wr[r])) =
+              make_float2(acc[2 * c][r], acc[2 * c + 1][r]);
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) *reinterpret_cast<float*>(lb + (h8 ^ wn[0] ^ wr[r])) = acc[0][r];
+    }
   }
 }
 
+// LIGHT: the split-BF16 matrix-core shapes with 2^nk >= 32 (the only ones
+// that need far more registers than the rest) are left out, so the kernel
+// has room to prefetch the next tile; the host launches it only for chains
+// without such steps (chain_needs_heavy).
+template <bool LIGHT>
 __device__ __forceinline__ void chain_step(karg_step& S, float2* buf, const float* sBf,
                                            const int32_t* rhi, bool split) {
   if (S.mfma && split) {
@@ -366,8 +422,10 @@ __device__ __forceinline__ void chain_step(karg_step& S, float2* buf, const floa
     TNK_CHAIN_MFMA(2, 3) TNK_CHAIN_MFMA(2, 4) TNK_CHAIN_MFMA(2, 5)
     TNK_CHAIN_MFMA(3, 3) TNK_CHAIN_MFMA(3, 4) TNK_CHAIN_MFMA(3, 5)
     TNK_CHAIN_MFMA(4, 3) TNK_CHAIN_MFMA(4, 4) TNK_CHAIN_MFMA(4, 5)
-    TNK_CHAIN_MFMA(5, 3) TNK_CHAIN_MFMA(5, 4)
-    TNK_CHAIN_MFMA(6, 3)
+    if constexpr (!LIGHT) {
+      TNK_CHAIN_MFMA(5, 3) TNK_CHAIN_MFMA(5, 4)
+      TNK_CHAIN_MFMA(6, 3)
+    }
 #undef TNK_CHAIN_MFMA
   }
   if (S.mfma) {
@@ -409,7 +467,8 @@ __device__ __forceinline__ void chain_stage_mfma_sb(karg_step& S, const float2* 
   for (int i = threadIdx.x; i < cnt; i += 256) {
     const int lane = i & 63, s2 = (i >> 6) % KS, cb = (i >> 6) / KS;
     const int g = lane >> 4, li = lane & 15;
-    const int jj = 16 * cb + li, n = jj >> 1, q = jj & 1;
+    int n, q;
+    chain_col(cb, li, CB, n, q);
     float v[4];
     for (int j = 0; j < 4; ++j) {
       const int kr = 16 * s2 + 4 * g + j, k = kr >> 1, p = kr & 1;
@@ -429,25 +488,29 @@ __device__ __forceinline__ void chain_stage_mfma_sb(karg_step& S, const float2* 
 
 // Stage the small operand of a matrix-core step as B' in the lanes' read
 // order: float i is lane i % 64, k step (i / 64) % KS, column block
-// i / (64 KS); lane (g, li) holds real column 16 cb + li (complex n, part q)
-// and real k row s of lane group g (complex k = g K/4 + s/2, part p).
+// i / (64 KS); lane (g, li) holds the real column of chain_col (complex n,
+// part q) and real k row s of lane group g (complex k = g K/4 + s/2, part p).
 __device__ __forceinline__ void chain_stage_mfma(karg_step& S, const float2* B, float* dst) {
   const int nk = S.nk, nn = S.nn, K = 1 << nk;
-  const int KG = K / 4, KS = K / 2;
+  const int KG = K / 4, KS = K / 2, CB = (1 << nn) / 8;
   const int cnt = 4 << (nk + nn);
   for (int i = threadIdx.x; i < cnt; i += 256) {
     const int lane = i & 63, s2 = (i >> 6) % KS, cb = (i >> 6) / KS;
     const int g = lane >> 4, li = lane & 15;
-    const int jj = 16 * cb + li, n = jj >> 1, q = jj & 1;
+    int n, q;
+    chain_col(cb, li, CB, n, q);
     const int k = g * KG + (s2 >> 1), p = s2 & 1;
     const float2 b = B[chain_off(k, S.kB, 0, nk) + chain_off(n, S.nB, 0, nn)];
     dst[i] = p ? (q ? b.x : -b.y) : (q ? b.y : b.x);
   }
 }
 
-template <int TB>
+// LIGHT (see chain_step): the next tile's input is loaded into registers
+// while this tile's steps run, so its latency overlaps the arithmetic.
+template <int TB, bool LIGHT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 k_chain(ChainArgs) {
+  constexpr bool PF = LIGHT;
   using Tab = ChainTables<TB>;
   constexpr int E = Tab::E;                        // tile elements per thread, at most
   constexpr int EB = E < 8 ? E : 8;                // loads in flight per batch
@@ -495,8 +558,14 @@ k_chain(ChainArgs) {
   const uint64_t n_tiles = 1ull << npas;
   __syncthreads();
   bool staged = false;
+  float2 pf[PF ? E : 1];
+  if (PF && blockIdx.x < n_tiles) {
+    const int64_t bx = bx_lo + chain_off(blockIdx.x, g.pas_in, lg, npas);
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if ((uint32_t)(e << 8) + tid < n_in) pf[e] = g.X[bx + xin_lo + tab.ein[e]];
+  }
   for (uint64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-    const int64_t bx = bx_lo + chain_off(t, g.pas_in, lg, npas);
     const int64_t by = by_lo + chain_off(t, g.pas_out, lg, npas);
     // small operands: [n][k] complex (vector steps) or B' (matrix steps)
     if (!staged || g.b_per_tile) {
@@ -518,22 +587,39 @@ k_chain(ChainArgs) {
       }
       staged = true;
     }
-    // load the input tile, eight loads per thread in flight at a time
+    if (PF) {
+      // the prefetched tile into LDS, then the next tile's loads
 #pragma unroll
-    for (int e0 = 0; e0 < E; e0 += EB) {
-      float2 v[EB];
+      for (int e = 0; e < E; ++e)
+        if ((uint32_t)(e << 8) + tid < n_in)
+          *reinterpret_cast<float2*>(lb + (lin8 ^ tab.lin[e])) = pf[e];
+      __syncthreads();
+      const uint64_t tn = t + gridDim.x;
+      if (tn < n_tiles) {
+        const int64_t bx = bx_lo + chain_off(tn, g.pas_in, lg, npas);
 #pragma unroll
-      for (int e = 0; e < EB; ++e)
-        if ((uint32_t)((e0 + e) << 8) + tid < n_in) v[e] = g.X[bx + xin_lo + tab.ein[e0 + e]];
+        for (int e = 0; e < E; ++e)
+          if ((uint32_t)(e << 8) + tid < n_in) pf[e] = g.X[bx + xin_lo + tab.ein[e]];
+      }
+    } else {
+      // load the input tile, eight loads per thread in flight at a time
+      const int64_t bx = bx_lo + chain_off(t, g.pas_in, lg, npas);
 #pragma unroll
-      for (int e = 0; e < EB; ++e)
-        if ((uint32_t)((e0 + e) << 8) + tid < n_in)
-          *reinterpret_cast<float2*>(lb + (lin8 ^ tab.lin[e0 + e])) = v[e];
+      for (int e0 = 0; e0 < E; e0 += EB) {
+        float2 v[EB];
+#pragma unroll
+        for (int e = 0; e < EB; ++e)
+          if ((uint32_t)((e0 + e) << 8) + tid < n_in) v[e] = g.X[bx + xin_lo + tab.ein[e0 + e]];
+#pragma unroll
+        for (int e = 0; e < EB; ++e)
+          if ((uint32_t)((e0 + e) << 8) + tid < n_in)
+            *reinterpret_cast<float2*>(lb + (lin8 ^ tab.lin[e0 + e])) = v[e];
+      }
+      __syncthreads();
     }
-    __syncthreads();
     for (int q = 0; q < nsteps; ++q) {
       karg_step& S = g.st[q];
-      chain_step(S, buf, sBf + S.boff0, tab.rhi[q], g.split != 0);
+      chain_step<LIGHT>(S, buf, sBf + S.boff0, tab.rhi[q], g.split != 0);
       __syncthreads();
     }
     // store the output tile

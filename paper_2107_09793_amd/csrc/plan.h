@@ -75,6 +75,9 @@ inline bool chain_mfma_shape(int nk, int nn) {
 inline bool chain_step_mfma(int nk, int nn, int nrow, uint32_t flags) {
   return !(flags & 32u) && chain_mfma_shape(nk, nn) && nrow >= 4;
 }
+// Split-BF16 matrix-core chain steps with 2^nk >= 32 need the register-heavy
+// build of the chain kernel (the others run in the build that prefetches).
+inline bool chain_needs_heavy(int nk, bool mfma, bool split) { return mfma && split && nk >= 5; }
 // Floats a chain step stages: the complex entries (vector units), or B' in
 // the lanes' order, padded to 8 complex k (split-BF16 k steps cover 16 reals).
 inline int chain_staged_floats(int nk, int nn, bool mfma) {

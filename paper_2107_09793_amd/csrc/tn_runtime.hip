@@ -370,12 +370,17 @@ tn_status run_chain(const Ctx& c, const tn::ChainGroup& g, uint64_t outer_val,
   if (probe && !probe->done)
     for (int k = g.first; k <= g.last; ++k) timed |= probe->step == k;
   if (timed) TN_HIP_CHECK(hipEventRecord(probe->start, c.st));
+  bool heavy = false;
+  for (int q = 0; q < a.nsteps; ++q)
+    heavy |= tn::chain_needs_heavy(a.st[q].nk, a.st[q].mfma != 0, a.split != 0);
   if (g.tile_bits <= 10)
-    hipLaunchKernelGGL(tnk::k_chain<10>, dim3(grid), dim3(256), 0, c.st, a);
+    hipLaunchKernelGGL((tnk::k_chain<10, false>), dim3(grid), dim3(256), 0, c.st, a);
   else if (g.tile_bits == 11)
-    hipLaunchKernelGGL(tnk::k_chain<11>, dim3(grid), dim3(256), 0, c.st, a);
+    hipLaunchKernelGGL((tnk::k_chain<11, false>), dim3(grid), dim3(256), 0, c.st, a);
+  else if (heavy)
+    hipLaunchKernelGGL((tnk::k_chain<12, false>), dim3(grid), dim3(256), 0, c.st, a);
   else
-    hipLaunchKernelGGL(tnk::k_chain<12>, dim3(grid), dim3(256), 0, c.st, a);
+    hipLaunchKernelGGL((tnk::k_chain<12, true>), dim3(grid), dim3(256), 0, c.st, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(TN_E_HIP, std::string("chain launch: ") + hipGetErrorString(e));
   if (timed) {
