@@ -55,6 +55,9 @@ struct ChainArgs {
   int32_t in_slot[kChainTile], in_log2[kChainTile];    // input tile bits, input-stride order
   int32_t out_slot[kChainTile], out_log2[kChainTile];  // output tile bits, output-stride order
   int32_t pas_in[kChainPas], pas_out[kChainPas];       // passive bits: X / Y strides
+  // with t = blockIdx.x + m gridDim.x: X / Y offset change from tile m to
+  // m + 1 is din / dout[ctz(m + 1)]
+  int64_t din[kChainPas], dout[kChainPas];
   ChainStepArgs st[kChainSteps];
 };
 
@@ -92,11 +95,55 @@ __device__ __forceinline__ int32_t chain_swz(int32_t x) {
 
 // Per-workgroup tables, built once before the tile loop: everything that
 // does not depend on the tile.
+#define TNK_GLOBAL __attribute__((address_space(1)))
+typedef float chain_f2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 chain_ld(const TNK_GLOBAL chain_f2* p, int64_t i) {
+  const chain_f2 v = p[i];
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void chain_st(TNK_GLOBAL chain_f2* p, int64_t i, float2 v) {
+  p[i] = chain_f2{v.x, v.y};
+}
+
+// Offsets of tile element (e << 8) + tid: the part of the high bits e is
+// linear in those bits, so it is kept as one term per bit (HBM offsets add,
+// swizzled LDS byte offsets XOR) and formed on the scalar unit per element.
+struct ChainElemOffsets {
+  int32_t o[4];   // log2 strides of element bits 8.. (bits beyond the tile are never set)
+  int32_t l[4];
+  __device__ __forceinline__ ChainElemOffsets(const karg_i32* log2s, const karg_i32* slots, int n) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      o[b] = 8 + b < n ? log2s[8 + b] : 0;
+      l[b] = 8 + b < n ? 8 * chain_swz(1 << slots[8 + b]) : 0;
+    }
+  }
+  // Makes the terms opaque to the compiler at this point, so offsets are
+  // formed where they are used instead of being hoisted (and kept live)
+  // out of the tile loop.
+  __device__ __forceinline__ void refresh() {
+    asm volatile("" : "+s"(o[0]), "+s"(o[1]), "+s"(o[2]), "+s"(o[3]));
+    asm volatile("" : "+s"(l[0]), "+s"(l[1]), "+s"(l[2]), "+s"(l[3]));
+  }
+  __device__ __forceinline__ int64_t hbm(int e) const {
+    int64_t r = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      if ((e >> b) & 1) r += (int64_t)1 << o[b];
+    return r;
+  }
+  __device__ __forceinline__ int32_t lds(int e) const {
+    int32_t r = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      if ((e >> b) & 1) r ^= l[b];
+    return r;
+  }
+};
+
 template <int TB>
 struct ChainTables {
   static constexpr int E = TB > 8 ? 1 << (TB - 8) : 1;
-  int64_t ein[E], eout[E];          // HBM offsets of tile element bits 8..
-  int32_t lin[E], lout[E];          // their swizzled LDS byte offsets
   int32_t boff[kChainV];            // small-operand offsets of staged entries (vector steps)
   int32_t rhi[kChainSteps][64];     // row bits >= 8 (vector steps) or >= 4 (matrix steps)
 };
@@ -160,6 +207,25 @@ __device__ __forceinline__ void chain_rows(karg_step& S, float2* buf, const floa
 // matrix core's order, not the stream kernel's.
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
+// Byte offset (times 8, swizzled) of the high row part of 16-row block rb:
+// the bits of rb sit at row slots rslot[4..nrow-1], and since the swizzle is
+// XOR-linear the offset is the XOR of one term per set bit of rb.  Block
+// numbers are wave-uniform, so this runs on the scalar unit.
+struct ChainBlockRows {
+  int32_t H[6];
+  __device__ __forceinline__ explicit ChainBlockRows(karg_step& S) {
+#pragma unroll
+    for (int t = 0; t < 6; ++t) H[t] = t + 4 < S.nrow ? 8 * chain_swz(1 << S.rslot[4 + t]) : 0;
+  }
+  __device__ __forceinline__ int32_t operator()(uint32_t rb) const {
+    int32_t h = 0;
+#pragma unroll
+    for (int t = 0; t < 6; ++t)
+      if ((rb >> t) & 1u) h ^= H[t];
+    return h;
+  }
+};
+
 // Real output column of lane li in 16-column block cb.  With two or more
 // blocks, blocks 2c and 2c + 1 hold the real and imaginary parts of complex
 // columns 16 c .. 16 c + 15, so a lane ends with both parts of one value and
@@ -182,7 +248,9 @@ __device__ __forceinline__ void chain_rows_mfma(karg_step& S, float2* buf, const
   constexpr int KG = K / 4;          // complex k per lane group
   constexpr int KS = K / 2;          // k steps of 4 real values
   constexpr int CB = N / 8;          // 16-column blocks of the real output
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const ChainBlockRows brow(S);
   const int g = lane >> 4, li = lane & 15;
   // B' was staged as [cb][k step][lane] (see the staging in k_chain)
   const float* bw = sBf + lane;
@@ -247,17 +315,22 @@ __device__ __forceinline__ void chain_rows_mfma(karg_step& S, float2* buf, const
 #pragma unroll
     for (int i = 0; i < KS * CB; ++i) bv[i] = bw[i * 64];
   }
-  for (uint32_t rb = wave; rb < blocks; rb += 4) {
-    const int32_t h8 = 8 * chain_swz(rhi[rb]);
-    float2 a[KG];
+  // The next block's values are read while this block's products run (two
+  // register sets used in turn, when they fit); blocks have disjoint rows, so
+  // reading the next block before this one is written is safe.
+  constexpr bool DB = KG <= 4;
+  auto load = [&](uint32_t rb, int32_t& hh, float2 (&x)[KG]) {
+    hh = brow(rb);
 #pragma unroll
-    for (int j = 0; j < KG; ++j) a[j] = *reinterpret_cast<const float2*>(lb + (h8 ^ ra[j]));
+    for (int j = 0; j < KG; ++j) x[j] = *reinterpret_cast<const float2*>(lb + (hh ^ ra[j]));
+  };
+  auto block = [&](int32_t hh, const float2 (&x)[KG]) {
     floatx4 acc[CB];
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) acc[cb] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int s2 = 0; s2 < KS; ++s2) {
-      const float av = (s2 & 1) ? a[s2 >> 1].y : a[s2 >> 1].x;
+      const float av = (s2 & 1) ? x[s2 >> 1].y : x[s2 >> 1].x;
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb)
         acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
@@ -267,12 +340,33 @@ __device__ __forceinline__ void chain_rows_mfma(karg_step& S, float2* buf, const
 #pragma unroll
       for (int c = 0; c < CP; ++c)
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          *reinterpret_cast<float2*>(lb + (h8 ^ wn[c] ^ wr[r])) =
-              make_float2(acc[2 * c][r], acc[2 * c + 1][r]);
+        for (int r = 0; r < 4; ++r) {
+          float* o = reinterpret_cast<float*>(lb + (hh ^ wn[c] ^ wr[r]));
+          o[0] = acc[2 * c][r];
+          o[1] = acc[2 * c + 1][r];
+        }
     } else {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) *reinterpret_cast<float*>(lb + (h8 ^ wn[0] ^ wr[r])) = acc[0][r];
+      for (int r = 0; r < 4; ++r) *reinterpret_cast<float*>(lb + (hh ^ wn[0] ^ wr[r])) = acc[0][r];
+    }
+  };
+  if (DB) {
+    int32_t h0 = 0, h1 = 0;
+    float2 a0[KG], a1[KG];
+    if ((uint32_t)wave < blocks) load(wave, h0, a0);
+    for (uint32_t rb = wave; rb < blocks; rb += 8) {
+      if (rb + 4 < blocks) load(rb + 4, h1, a1);
+      block(h0, a0);
+      if (rb + 4 >= blocks) break;
+      if (rb + 8 < blocks) load(rb + 8, h0, a0);
+      block(h1, a1);
+    }
+  } else {
+    for (uint32_t rb = wave; rb < blocks; rb += 4) {
+      int32_t h0;
+      float2 a0[KG];
+      load(rb, h0, a0);
+      block(h0, a0);
     }
   }
 }
@@ -301,7 +395,9 @@ __device__ __forceinline__ void chain_rows_mfma_sb(karg_step& S, float2* buf, co
   constexpr int K = 1 << NK, N = 1 << NN;
   constexpr int KS = K >= 8 ? K / 8 : 1;   // k steps of 16 real values
   constexpr int CB = N / 8;                // 16-column blocks of the real output
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const ChainBlockRows brow(S);
   const int g = lane >> 4, li = lane & 15;
   const shortx4* bh = reinterpret_cast<const shortx4*>(sBf) + lane;
   const shortx4* bl = bh + CB * KS * 64;
@@ -366,16 +462,23 @@ __device__ __forceinline__ void chain_rows_mfma_sb(karg_step& S, float2* buf, co
       rl[i] = bl[i * 64];
     }
   }
-  for (uint32_t rb = wave; rb < blocks; rb += 4) {
-    const int32_t h8 = 8 * chain_swz(rhi[rb]);
+  // as in the FP32 variant: the next block's values are read early (two
+  // register sets used in turn, when they fit)
+  constexpr bool DB = KS <= 2;
+  auto load = [&](uint32_t rb, int32_t& hh, float2 (&x)[KS][2]) {
+    hh = brow(rb);
+#pragma unroll
+    for (int s2 = 0; s2 < KS; ++s2)
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+        x[s2][e] = kok[s2][e] ? *reinterpret_cast<const float2*>(lb + (hh ^ ra[s2][e]))
+                              : make_float2(0.f, 0.f);
+  };
+  auto block = [&](int32_t hh, const float2 (&x)[KS][2]) {
     shortx4 ah[KS], al[KS];
 #pragma unroll
     for (int s2 = 0; s2 < KS; ++s2) {
-      float2 a0 = kok[s2][0] ? *reinterpret_cast<const float2*>(lb + (h8 ^ ra[s2][0]))
-                             : make_float2(0.f, 0.f);
-      float2 a1 = kok[s2][1] ? *reinterpret_cast<const float2*>(lb + (h8 ^ ra[s2][1]))
-                             : make_float2(0.f, 0.f);
-      const f4v v = {a0.x, a0.y, a1.x, a1.y};
+      const f4v v = {x[s2][0].x, x[s2][0].y, x[s2][1].x, x[s2][1].y};
       chain_split4(v, ah[s2], al[s2]);
     }
     floatx4 acc[CB];
@@ -396,12 +499,33 @@ __device__ __forceinline__ void chain_rows_mfma_sb(karg_step& S, float2* buf, co
 #pragma unroll
       for (int c = 0; c < CP; ++c)
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          *reinterpret_cast<float2*>(lb + (h8 ^ wn[c] ^ wr[r])) =
-              make_float2(acc[2 * c][r], acc[2 * c + 1][r]);
+        for (int r = 0; r < 4; ++r) {
+          float* o = reinterpret_cast<float*>(lb + (hh ^ wn[c] ^ wr[r]));
+          o[0] = acc[2 * c][r];
+          o[1] = acc[2 * c + 1][r];
+        }
     } else {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) *reinterpret_cast<float*>(lb + (h8 ^ wn[0] ^ wr[r])) = acc[0][r];
+      for (int r = 0; r < 4; ++r) *reinterpret_cast<float*>(lb + (hh ^ wn[0] ^ wr[r])) = acc[0][r];
+    }
+  };
+  if (DB) {
+    int32_t h0 = 0, h1 = 0;
+    float2 a0[KS][2], a1[KS][2];
+    if ((uint32_t)wave < blocks) load(wave, h0, a0);
+    for (uint32_t rb = wave; rb < blocks; rb += 8) {
+      if (rb + 4 < blocks) load(rb + 4, h1, a1);
+      block(h0, a0);
+      if (rb + 4 >= blocks) break;
+      if (rb + 8 < blocks) load(rb + 8, h0, a0);
+      block(h1, a1);
+    }
+  } else {
+    for (uint32_t rb = wave; rb < blocks; rb += 4) {
+      int32_t h0;
+      float2 a0[KS][2];
+      load(rb, h0, a0);
+      block(h0, a0);
     }
   }
 }
@@ -521,13 +645,6 @@ k_chain(ChainArgs) {
   const int tid = threadIdx.x;
   const int nsteps = g.nsteps, npas = g.npas, tin = g.tin, tout = g.tout;
   // --- tables -------------------------------------------------------------
-  if (tid < E) {
-    const uint32_t e = (uint32_t)tid << 8;
-    tab.ein[tid] = chain_off(e, g.in_log2, 8, tin);
-    tab.eout[tid] = chain_off(e, g.out_log2, 8, tout);
-    tab.lin[tid] = 8 * chain_swz(chain_slot(e, g.in_slot, 8, tin));
-    tab.lout[tid] = 8 * chain_swz(chain_slot(e, g.out_slot, 8, tout));
-  }
   {
     for (int q = 0; q < nsteps; ++q) {
       karg_step& S = g.st[q];
@@ -544,7 +661,9 @@ k_chain(ChainArgs) {
     }
   }
   // tile numbers: t = blockIdx.x + m * gridDim.x with gridDim.x a power of two,
-  // so the low tile bits are this workgroup's and only the high ones vary
+  // so the low tile bits are this workgroup's and only the high ones (m)
+  // vary.  Going from m to m + 1 flips bits 0..c of m, c = ctz(m + 1): the
+  // tile's offsets change by din[c] / dout[c].
   const int lg = 31 - __builtin_clz(gridDim.x);
   const int64_t bx_lo = chain_off(blockIdx.x, g.pas_in, 0, lg < npas ? lg : npas);
   const int64_t by_lo = chain_off(blockIdx.x, g.pas_out, 0, lg < npas ? lg : npas);
@@ -555,18 +674,36 @@ k_chain(ChainArgs) {
   const int32_t lout8 = 8 * chain_swz(chain_slot(tid, g.out_slot, 0, lo_out));
   char* lb = reinterpret_cast<char*>(buf);
   const uint32_t n_in = 1u << tin, n_out = 1u << tout;
+  // elements per thread (uniform) and whether this thread has element 0
+  const int ne_in = tin > 8 ? 1 << (tin - 8) : 1, ne_out = tout > 8 ? 1 << (tout - 8) : 1;
+  const bool in_ok = (uint32_t)tid < n_in, out_ok = (uint32_t)tid < n_out;
+  ChainElemOffsets ei(g.in_log2, g.in_slot, tin), eo(g.out_log2, g.out_slot, tout);
+  // tensor base addresses, kept in scalar registers (refreshed per tile so
+  // they are not reloaded from the argument segment at every use)
+  uint64_t xa = (uint64_t)g.X, ya = (uint64_t)g.Y;
+  // a tile of 256 or more elements has every thread busy: the guards are
+  // then uniform (whole elements), else only element 0 of some threads
+  const bool lane_in = in_ok || tin >= 8, lane_out = out_ok || tout >= 8;
   const uint64_t n_tiles = 1ull << npas;
   __syncthreads();
   bool staged = false;
   float2 pf[PF ? E : 1];
   if (PF && blockIdx.x < n_tiles) {
-    const int64_t bx = bx_lo + chain_off(blockIdx.x, g.pas_in, lg, npas);
 #pragma unroll
     for (int e = 0; e < E; ++e)
-      if ((uint32_t)(e << 8) + tid < n_in) pf[e] = g.X[bx + xin_lo + tab.ein[e]];
+      if (e < ne_in && lane_in) pf[e] = chain_ld((const TNK_GLOBAL chain_f2*)xa, bx_lo + xin_lo + ei.hbm(e));
   }
-  for (uint64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-    const int64_t by = by_lo + chain_off(t, g.pas_out, lg, npas);
+  int64_t bx = bx_lo, by = by_lo;
+  uint64_t m = 0;
+  for (uint64_t t = blockIdx.x; t < n_tiles; t += gridDim.x, ++m) {
+    ei.refresh();
+    eo.refresh();
+    asm volatile("" : "+s"(xa), "+s"(ya));
+    const TNK_GLOBAL chain_f2* Xp = (const TNK_GLOBAL chain_f2*)xa;
+    TNK_GLOBAL chain_f2* Yp = (TNK_GLOBAL chain_f2*)ya;
+    const bool more = t + gridDim.x < n_tiles;
+    const int cm = more ? (int)__builtin_ctzll(m + 1) : 0;
+    const int64_t dbx = more ? g.din[cm] : 0, dby = more ? g.dout[cm] : 0;
     // small operands: [n][k] complex (vector steps) or B' (matrix steps)
     if (!staged || g.b_per_tile) {
       for (int q = 0; q < nsteps; ++q) {
@@ -591,29 +728,26 @@ k_chain(ChainArgs) {
       // the prefetched tile into LDS, then the next tile's loads
 #pragma unroll
       for (int e = 0; e < E; ++e)
-        if ((uint32_t)(e << 8) + tid < n_in)
-          *reinterpret_cast<float2*>(lb + (lin8 ^ tab.lin[e])) = pf[e];
+        if (e < ne_in && lane_in) *reinterpret_cast<float2*>(lb + (lin8 ^ ei.lds(e))) = pf[e];
       __syncthreads();
-      const uint64_t tn = t + gridDim.x;
-      if (tn < n_tiles) {
-        const int64_t bx = bx_lo + chain_off(tn, g.pas_in, lg, npas);
+      if (more) {
+        const int64_t bxn = bx + dbx;
 #pragma unroll
         for (int e = 0; e < E; ++e)
-          if ((uint32_t)(e << 8) + tid < n_in) pf[e] = g.X[bx + xin_lo + tab.ein[e]];
+          if (e < ne_in && lane_in) pf[e] = chain_ld(Xp, bxn + xin_lo + ei.hbm(e));
       }
     } else {
       // load the input tile, eight loads per thread in flight at a time
-      const int64_t bx = bx_lo + chain_off(t, g.pas_in, lg, npas);
 #pragma unroll
       for (int e0 = 0; e0 < E; e0 += EB) {
         float2 v[EB];
 #pragma unroll
         for (int e = 0; e < EB; ++e)
-          if ((uint32_t)((e0 + e) << 8) + tid < n_in) v[e] = g.X[bx + xin_lo + tab.ein[e0 + e]];
+          if (e0 + e < ne_in && lane_in) v[e] = chain_ld(Xp, bx + xin_lo + ei.hbm(e0 + e));
 #pragma unroll
         for (int e = 0; e < EB; ++e)
-          if ((uint32_t)((e0 + e) << 8) + tid < n_in)
-            *reinterpret_cast<float2*>(lb + (lin8 ^ tab.lin[e0 + e])) = v[e];
+          if (e0 + e < ne_in && lane_in)
+            *reinterpret_cast<float2*>(lb + (lin8 ^ ei.lds(e0 + e))) = v[e];
       }
       __syncthreads();
     }
@@ -628,13 +762,15 @@ k_chain(ChainArgs) {
       float2 v[EB];
 #pragma unroll
       for (int e = 0; e < EB; ++e)
-        if ((uint32_t)((e0 + e) << 8) + tid < n_out)
-          v[e] = *reinterpret_cast<const float2*>(lb + (lout8 ^ tab.lout[e0 + e]));
+        if (e0 + e < ne_out && lane_out)
+          v[e] = *reinterpret_cast<const float2*>(lb + (lout8 ^ eo.lds(e0 + e)));
 #pragma unroll
       for (int e = 0; e < EB; ++e)
-        if ((uint32_t)((e0 + e) << 8) + tid < n_out) g.Y[by + yout_lo + tab.eout[e0 + e]] = v[e];
+        if (e0 + e < ne_out && lane_out) chain_st(Yp, by + yout_lo + eo.hbm(e0 + e), v[e]);
     }
     __syncthreads();
+    bx += dbx;
+    by += dby;
   }
 }
 

@@ -110,6 +110,111 @@ struct StepBits {  // global bit ids of a step's classes, in stride-array order
 };
 
 
+// LDS bank spread of a matrix-core chain step.  The chain kernel's LDS
+// address of tile position x is 8 swz(x) bytes, swz(x) = x ^ ((x >> 5 ^
+// x >> 9) & 31), so with 64 four-byte banks the bank pair of x is
+// swz(x) & 31, an XOR-linear function: a tile slot contributes a fixed
+// 5-bit vector.  Thirty-two lanes that vary over five slot bits hit
+// 2^(5 - rank) times the same bank pair.  The step's roles can be chosen
+// freely: which four row slots form a 16-row block (and which of them is
+// the lane group's low output-row bit), which summed slot the lane group's
+// low bit takes, and which four new slots the 16 lanes of a column block
+// cover; this picks the choice with the fewest repeated banks for the
+// block's reads and writes.
+static uint32_t bank_vec(int slot) {
+  const uint32_t x = 1u << slot;
+  return (x ^ (x >> 5) ^ (x >> 9)) & 31u;
+}
+
+static int gf2_rank(std::vector<uint32_t> v) {
+  int r = 0;
+  for (int bit = 31; bit >= 0; --bit) {
+    int piv = -1;
+    for (int i = r; i < (int)v.size(); ++i)
+      if ((v[i] >> bit) & 1u) {
+        piv = i;
+        break;
+      }
+    if (piv < 0) continue;
+    std::swap(v[r], v[piv]);
+    for (int i = 0; i < (int)v.size(); ++i)
+      if (i != r && ((v[i] >> bit) & 1u)) v[i] ^= v[r];
+    ++r;
+  }
+  return r;
+}
+
+static void bank_tune(ChainStepDesc& d, bool split) {
+  const int nk = (int)d.kslot.size(), nn = (int)d.nslot.size(), nrow = (int)d.rslot.size();
+  if (nrow < 4) return;
+  // lane group g's low bit is summed bit g0pos of the step (see the kernels)
+  const int g0pos = split ? 1 : nk - 2;
+  const int kg = nk >= 2 ? nk : 0;
+  const int CB = (1 << nn) / 8;
+  const int reads = split ? 2 * std::max(1, (1 << nk) / 8) : (1 << nk) / 4;
+  const int writes = CB >= 2 ? 2 * CB : 4;
+  double best = 1e30;
+  std::vector<int8_t> bR;
+  int bG = -1, bX = -1;
+  for (int a = 0; a < nrow; ++a)
+    for (int b = a + 1; b < nrow; ++b)
+      for (int c = b + 1; c < nrow; ++c)
+        for (int e = c + 1; e < nrow; ++e) {
+          const int four[4] = {a, b, c, e};
+          for (int r2 = 0; r2 < 4; ++r2) {
+            const int8_t R2 = d.rslot[four[r2]];
+            // writes: 32 lanes = 16 column lanes x the low lane-group bit
+            double wbest = 1e30;
+            int wx = -1;
+            for (int x = (nn == 5 ? 0 : -1); x < (nn == 5 ? 5 : 0); ++x) {
+              std::vector<uint32_t> v;
+              if (CB >= 2) {
+                for (int t = 0; t < nn; ++t)
+                  if (t != x && (int)v.size() < 4) v.push_back(bank_vec(d.nslot[t]));
+              } else {
+                for (int t = 0; t < 3 && t < nn; ++t) v.push_back(bank_vec(d.nslot[t]));
+              }
+              v.push_back(bank_vec(R2));
+              const double m = (double)(1 << ((int)v.size() - gf2_rank(v)));
+              if (m < wbest) {
+                wbest = m;
+                wx = x;
+              }
+            }
+            for (int gk = 0; gk < kg; ++gk) {
+              std::vector<uint32_t> v;
+              for (int t = 0; t < 4; ++t) v.push_back(bank_vec(d.rslot[four[t]]));
+              v.push_back(bank_vec(d.kslot[gk]));
+              const double rm = (double)(1 << (5 - gf2_rank(v)));
+              const double cost = reads * rm + writes * wbest;
+              if (cost < best - 1e-9) {
+                best = cost;
+                bR.clear();
+                for (int t = 0; t < 4; ++t)
+                  if (t != r2) bR.push_back(d.rslot[four[t]]);
+                bR.insert(bR.begin() + 2, R2);   // rows: r bits 0, 1, then g bits
+                bG = gk;
+                bX = wx;
+              }
+            }
+          }
+        }
+  if (bG < 0) return;
+  std::vector<int8_t> rest;
+  for (int8_t s : d.rslot)
+    if (std::find(bR.begin(), bR.end(), s) == bR.end()) rest.push_back(s);
+  d.rslot = bR;
+  d.rslot.insert(d.rslot.end(), rest.begin(), rest.end());
+  if (g0pos >= 0 && g0pos < nk && bG != g0pos) {
+    std::swap(d.kslot[g0pos], d.kslot[bG]);
+    std::swap(d.kB[g0pos], d.kB[bG]);
+  }
+  if (bX >= 0 && bX != 4) {
+    std::swap(d.nslot[4], d.nslot[bX]);
+    std::swap(d.nB[4], d.nB[bX]);
+  }
+}
+
 // Tile of a chain candidate first..last (see ChainGroup); returns false when
 // it does not fit the LDS tile or a summed / batch bit is misplaced.
 bool build_chain(const Plan& p, const std::vector<Layout>& lay, const std::vector<StepBits>& sb,
@@ -239,6 +344,7 @@ bool build_chain(const Plan& p, const std::vector<Layout>& lay, const std::vecto
     d.kB = S.kB;
     d.nB = S.nB;
     d.bB = S.bB;
+    if (on_mfma) bank_tune(d, p.precision == PREC_SPLIT_BF16);
     for (int32_t b : sb[k].batch) {
       auto it = std::find(pt.begin(), pt.end(), b);
       if (it == pt.end()) return false;

@@ -363,6 +363,20 @@ tn_status run_chain(const Ctx& c, const tn::ChainGroup& g, uint64_t outer_val,
     return fail(TN_E_INVALID, "chain exceeds its on-chip limits");
   const uint64_t n_tiles = 1ull << a.npas;
   const unsigned grid = (unsigned)std::min<uint64_t>(n_tiles, 1u << 16);
+  {
+    int lg = 0;
+    while ((1u << (lg + 1)) <= grid) ++lg;
+    int64_t si = 0, so = 0;
+    for (int c = 0; c < tnk::kChainPas; ++c) {
+      a.din[c] = a.dout[c] = 0;
+      if (lg + c < a.npas) {
+        a.din[c] = ((int64_t)1 << a.pas_in[lg + c]) - si;
+        a.dout[c] = ((int64_t)1 << a.pas_out[lg + c]) - so;
+        si += (int64_t)1 << a.pas_in[lg + c];
+        so += (int64_t)1 << a.pas_out[lg + c];
+      }
+    }
+  }
   bool timed = false;
   static_assert(sizeof(a.st[0].kslot) / sizeof(a.st[0].kslot[0]) >= 6 &&
                     sizeof(a.st[0].nslot) / sizeof(a.st[0].nslot[0]) >= 6,
