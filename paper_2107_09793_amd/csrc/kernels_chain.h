@@ -686,7 +686,6 @@ k_chain(ChainArgs) {
   const bool lane_in = in_ok || tin >= 8, lane_out = out_ok || tout >= 8;
   const uint64_t n_tiles = 1ull << npas;
   __syncthreads();
-  bool staged = false;
   float2 pf[PF ? E : 1];
   if (PF && blockIdx.x < n_tiles) {
 #pragma unroll
@@ -695,6 +694,17 @@ k_chain(ChainArgs) {
   }
   int64_t bx = bx_lo, by = by_lo;
   uint64_t m = 0;
+  // Small operands that depend on batch bits of the tile number are staged
+  // again only when such a bit changes: bits below lg are this workgroup's
+  // and never change; bit lg + b flips from tile m to m + 1 iff b <= ctz(m+1).
+  int bmin = 64;
+  if (g.b_per_tile)
+    for (int q = 0; q < nsteps; ++q)
+      for (int j = 0; j < g.st[q].nbb; ++j) {
+        const int b = g.st[q].bpas[j] - lg;
+        if (b >= 0 && b < bmin) bmin = b;
+      }
+  bool restage = true;
   for (uint64_t t = blockIdx.x; t < n_tiles; t += gridDim.x, ++m) {
     ei.refresh();
     eo.refresh();
@@ -705,7 +715,7 @@ k_chain(ChainArgs) {
     const int cm = more ? (int)__builtin_ctzll(m + 1) : 0;
     const int64_t dbx = more ? g.din[cm] : 0, dby = more ? g.dout[cm] : 0;
     // small operands: [n][k] complex (vector steps) or B' (matrix steps)
-    if (!staged || g.b_per_tile) {
+    if (restage) {
       for (int q = 0; q < nsteps; ++q) {
         karg_step& S = g.st[q];
         int64_t bb = 0;
@@ -722,8 +732,9 @@ k_chain(ChainArgs) {
           for (int i = tid; i < cnt; i += 256) dst[i] = B[tab.boff[S.voff0 + i]];
         }
       }
-      staged = true;
+      restage = false;
     }
+    restage = more && cm >= bmin;
     if (PF) {
       // the prefetched tile into LDS, then the next tile's loads
 #pragma unroll
