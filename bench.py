@@ -98,24 +98,27 @@ def dominant_unit(plan, leaves, info, units, torch):
 def roofline(unit, avg_s, precision):
     """The unit's bound is the larger of its HBM time (algorithmic bytes at
     8 TB/s) and its compute time (MFMA for GEMM steps at the precision's
-    peak, counting the three products of split-BF16; FP32 MFMA or FP32
-    vector FMA for chain steps, as the chain runs them; FP32 vector FMA for
-    the others); achieved is measured in that bound's unit against the peak
-    of the units doing most of the work."""
+    peak, counting the three products of split-BF16; for chain steps MFMA
+    at the precision's peak or FP32 vector FMA, as the chain runs them;
+    FP32 vector FMA for the others); achieved is measured in that bound's
+    unit against the peak of the units doing most of the work."""
     kind = unit["kind"]
     if kind == "gemm":
         flops = 8.0 * unit["cmac"] * (3.0 if precision == "split_bf16" else 1.0)
         peak, cbound = PEAKS["mfma_" + precision], "mfma"
         t_cmp = flops / (peak * 1e12)
     elif kind == "chain":
-        # chain steps run on FP32 matrix cores or FP32 vector units
-        flops = 8.0 * unit["cmac"]
+        # chain steps run on the matrix cores (FP32, or three BF16 products
+        # in split-BF16 plans) or on the FP32 vector units
         fm = 8.0 * unit["cmac_mfma"]
-        t_cmp = fm / (PEAKS["mfma_c64"] * 1e12) + (flops - fm) / (PEAKS["alu"] * 1e12)
-        if fm >= flops - fm:
-            peak, cbound = PEAKS["mfma_c64"], "mfma"
+        fv = 8.0 * unit["cmac"] - fm
+        mpeak = PEAKS["mfma_" + precision]
+        fm_exec = fm * (3.0 if precision == "split_bf16" else 1.0)
+        t_cmp = fm_exec / (mpeak * 1e12) + fv / (PEAKS["alu"] * 1e12)
+        if fm_exec / mpeak >= fv / PEAKS["alu"]:
+            flops, peak, cbound = fm_exec + fv, mpeak, "mfma"
         else:
-            peak, cbound = PEAKS["alu"], "alu"
+            flops, peak, cbound = fm_exec + fv, PEAKS["alu"], "alu"
     else:
         flops = 8.0 * unit["cmac"]
         peak, cbound = PEAKS["alu"], "alu"
