@@ -141,17 +141,10 @@ struct ChainElemOffsets {
   }
 };
 
-template <int TB>
-struct ChainTables {
-  static constexpr int E = TB > 8 ? 1 << (TB - 8) : 1;
-  int32_t boff[kChainV];            // small-operand offsets of staged entries (vector steps)
-  int32_t rhi[kChainSteps][64];     // row bits >= 8 (vector steps) or >= 4 (matrix steps)
-};
 
 // small operand of a step staged as [n][k]
 template <int NK, int NN>
-__device__ __forceinline__ void chain_rows(karg_step& S, float2* buf, const float2* sB,
-                                           const int32_t* rhi) {
+__device__ __forceinline__ void chain_rows(karg_step& S, float2* buf, const float2* sB) {
   constexpr int K = 1 << NK, N = 1 << NN;
   int32_t koff[K];
 #pragma unroll
@@ -172,7 +165,10 @@ __device__ __forceinline__ void chain_rows(karg_step& S, float2* buf, const floa
     if (j < nrow) rlo |= ((threadIdx.x >> j) & 1) << S.rslot[j];
   for (uint32_t r0 = 0; r0 < rows; r0 += 256) {
     if (r0 + threadIdx.x >= rows) break;
-    const int32_t base = rlo | rhi[r0 >> 8];
+    // rows of 256-row group r0 / 256: its bits sit at row slots 8..nrow-1
+    int32_t rh = 0;
+    for (int j = 8; j < nrow; ++j) rh |= (int32_t)((r0 >> j) & 1u) << S.rslot[j];
+    const int32_t base = rlo | rh;
     float2 a[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) a[k] = buf[chain_swz(base | koff[k])];
@@ -242,8 +238,7 @@ __device__ __forceinline__ void chain_col(int cb, int li, int CB, int& n, int& q
 }
 
 template <int NK, int NN>
-__device__ __forceinline__ void chain_rows_mfma(karg_step& S, float2* buf, const float* sBf,
-                                                const int32_t* rhi) {
+__device__ __forceinline__ void chain_rows_mfma(karg_step& S, float2* buf, const float* sBf) {
   constexpr int K = 1 << NK, N = 1 << NN;
   constexpr int KG = K / 4;          // complex k per lane group
   constexpr int KS = K / 2;          // k steps of 4 real values
@@ -390,8 +385,7 @@ __device__ __forceinline__ void chain_split4(f4v v, shortx4& hi, shortx4& lo) {
 }
 
 template <int NK, int NN>
-__device__ __forceinline__ void chain_rows_mfma_sb(karg_step& S, float2* buf, const float* sBf,
-                                                   const int32_t* rhi) {
+__device__ __forceinline__ void chain_rows_mfma_sb(karg_step& S, float2* buf, const float* sBf) {
   constexpr int K = 1 << NK, N = 1 << NN;
   constexpr int KS = K >= 8 ? K / 8 : 1;   // k steps of 16 real values
   constexpr int CB = N / 8;                // 16-column blocks of the real output
@@ -530,51 +524,54 @@ __device__ __forceinline__ void chain_rows_mfma_sb(karg_step& S, float2* buf, co
   }
 }
 
-// LIGHT: the split-BF16 matrix-core shapes with 2^nk >= 32 (the only ones
-// that need far more registers than the rest) are left out, so the kernel
-// has room to prefetch the next tile; the host launches it only for chains
-// without such steps (chain_needs_heavy).
-template <bool LIGHT>
-__device__ __forceinline__ void chain_step(karg_step& S, float2* buf, const float* sBf,
-                                           const int32_t* rhi, bool split) {
-  if (S.mfma && split) {
+// Builds of the chain kernel (CLS):
+//  0  every step shape, no prefetch;
+//  1  no split-BF16 matrix-core step with 2^nk >= 32 (the only shapes that
+//     need far more registers than the rest): room to prefetch the next tile;
+//  2  small shapes only (chain_small_step): few enough registers for 4 waves
+//     per SIMD, used when the chain's staged operands also leave room for 4
+//     workgroups per CU.
+// The host picks the build from the chain's steps (chain_build_class).
+__host__ __device__ constexpr bool chain_small_step(int nk, int nn, bool mfma) {
+  return mfma ? (nk <= 4 && nn <= 4) : (nk <= 3 && nn <= 4);
+}
+
+template <int CLS>
+__device__ __forceinline__ void chain_step(karg_step& S, float2* buf, const float* sBf, bool split) {
+  constexpr bool LIGHT = CLS != 0, SMALL = CLS == 2;
 #define TNK_CHAIN_MFMA(A, B)                      \
   if (S.nk == A && S.nn == B) {                   \
-    chain_rows_mfma_sb<A, B>(S, buf, sBf, rhi);   \
+    if (split)                                    \
+      chain_rows_mfma_sb<A, B>(S, buf, sBf);      \
+    else                                          \
+      chain_rows_mfma<A, B>(S, buf, sBf);         \
     return;                                       \
   }
-    TNK_CHAIN_MFMA(2, 3) TNK_CHAIN_MFMA(2, 4) TNK_CHAIN_MFMA(2, 5)
-    TNK_CHAIN_MFMA(3, 3) TNK_CHAIN_MFMA(3, 4) TNK_CHAIN_MFMA(3, 5)
-    TNK_CHAIN_MFMA(4, 3) TNK_CHAIN_MFMA(4, 4) TNK_CHAIN_MFMA(4, 5)
-    if constexpr (!LIGHT) {
-      TNK_CHAIN_MFMA(5, 3) TNK_CHAIN_MFMA(5, 4)
-      TNK_CHAIN_MFMA(6, 3)
-    }
-#undef TNK_CHAIN_MFMA
-  }
   if (S.mfma) {
-#define TNK_CHAIN_MFMA(A, B)                   \
-  if (S.nk == A && S.nn == B) {                \
-    chain_rows_mfma<A, B>(S, buf, sBf, rhi);   \
-    return;                                    \
+    TNK_CHAIN_MFMA(2, 3) TNK_CHAIN_MFMA(2, 4) TNK_CHAIN_MFMA(3, 3) TNK_CHAIN_MFMA(3, 4)
+    TNK_CHAIN_MFMA(4, 3) TNK_CHAIN_MFMA(4, 4)
+    if constexpr (!SMALL) {
+      TNK_CHAIN_MFMA(2, 5) TNK_CHAIN_MFMA(3, 5) TNK_CHAIN_MFMA(4, 5)
+      if (!split || !LIGHT) {
+        TNK_CHAIN_MFMA(5, 3) TNK_CHAIN_MFMA(5, 4)
+        TNK_CHAIN_MFMA(6, 3)
+      }
+    }
   }
-    TNK_CHAIN_MFMA(2, 3) TNK_CHAIN_MFMA(2, 4) TNK_CHAIN_MFMA(2, 5)
-    TNK_CHAIN_MFMA(3, 3) TNK_CHAIN_MFMA(3, 4) TNK_CHAIN_MFMA(3, 5)
-    TNK_CHAIN_MFMA(4, 3) TNK_CHAIN_MFMA(4, 4) TNK_CHAIN_MFMA(4, 5)
-    TNK_CHAIN_MFMA(5, 3) TNK_CHAIN_MFMA(5, 4)
-    TNK_CHAIN_MFMA(6, 3)
 #undef TNK_CHAIN_MFMA
-  }
   const float2* sB = reinterpret_cast<const float2*>(sBf);
   // the per-step stream kernel covers nk, nn in 0..4; so does the chain
 #define TNK_CHAIN_CASE(A, B)                \
   if (S.nk == A && S.nn == B) {             \
-    chain_rows<A, B>(S, buf, sB, rhi);      \
+    chain_rows<A, B>(S, buf, sB);           \
     return;                                 \
   }
 #define TNK_CHAIN_ROW(A) \
   TNK_CHAIN_CASE(A, 0) TNK_CHAIN_CASE(A, 1) TNK_CHAIN_CASE(A, 2) TNK_CHAIN_CASE(A, 3) TNK_CHAIN_CASE(A, 4)
-  TNK_CHAIN_ROW(0) TNK_CHAIN_ROW(1) TNK_CHAIN_ROW(2) TNK_CHAIN_ROW(3) TNK_CHAIN_ROW(4)
+  TNK_CHAIN_ROW(0) TNK_CHAIN_ROW(1) TNK_CHAIN_ROW(2) TNK_CHAIN_ROW(3)
+  if constexpr (!SMALL) {
+    TNK_CHAIN_ROW(4)
+  }
 #undef TNK_CHAIN_ROW
 #undef TNK_CHAIN_CASE
 }
@@ -629,37 +626,25 @@ __device__ __forceinline__ void chain_stage_mfma(karg_step& S, const float2* B, 
   }
 }
 
-// LIGHT (see chain_step): the next tile's input is loaded into registers
-// while this tile's steps run, so its latency overlaps the arithmetic.
-template <int TB, bool LIGHT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+// The staged small operands live in dynamic LDS sized per launch (the
+// floats ChainArgs::b_total), so chains with small operands leave room for
+// more workgroups per CU.
+extern __shared__ __attribute__((aligned(16))) float chain_staged[];
+
+// CLS (see chain_step): build 1 loads the next tile's input into registers
+// while this tile's steps run, so its latency overlaps the arithmetic;
+// build 2 runs at 4 waves per SIMD instead.
+template <int TB, int CLS>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CLS == 2 ? 4 : 3)))
 k_chain(ChainArgs) {
-  constexpr bool PF = LIGHT;
-  using Tab = ChainTables<TB>;
-  constexpr int E = Tab::E;                        // tile elements per thread, at most
+  constexpr bool PF = CLS == 1;
+  constexpr int E = TB > 8 ? 1 << (TB - 8) : 1;   // tile elements per thread, at most
   constexpr int EB = E < 8 ? E : 8;                // loads in flight per batch
   __shared__ float2 buf[1 << TB];
-  __shared__ __attribute__((aligned(16))) float sBf[kChainBF];
-  __shared__ Tab tab;
+  float* sBf = chain_staged;
   karg_chain& g = *(karg_chain*)__builtin_amdgcn_kernarg_segment_ptr();
   const int tid = threadIdx.x;
   const int nsteps = g.nsteps, npas = g.npas, tin = g.tin, tout = g.tout;
-  // --- tables -------------------------------------------------------------
-  {
-    for (int q = 0; q < nsteps; ++q) {
-      karg_step& S = g.st[q];
-      const int nk = S.nk, nn = S.nn, cnt = 1 << (nk + nn);
-      if (!S.mfma)
-        for (int i = tid; i < cnt; i += 256) {
-          const int n = i >> nk, k = i & ((1 << nk) - 1);
-          tab.boff[S.voff0 + i] = (int32_t)(chain_off(k, S.kB, 0, nk) + chain_off(n, S.nB, 0, nn));
-        }
-      // high row parts: per 256-row group (vector steps) or 16-row block
-      const int lo = S.mfma ? 4 : 8;
-      const int nhi = S.nrow > lo ? 1 << (S.nrow - lo) : 1;
-      for (int i = tid; i < nhi; i += 256) tab.rhi[q][i] = chain_slot((uint32_t)i << lo, S.rslot, lo, S.nrow);
-    }
-  }
   // tile numbers: t = blockIdx.x + m * gridDim.x with gridDim.x a power of two,
   // so the low tile bits are this workgroup's and only the high ones (m)
   // vary.  Going from m to m + 1 flips bits 0..c of m, c = ctz(m + 1): the
@@ -727,9 +712,12 @@ k_chain(ChainArgs) {
         } else if (S.mfma) {
           chain_stage_mfma(S, B, sBf + S.boff0);
         } else {
-          const int cnt = 1 << (S.nk + S.nn);
+          const int nk = S.nk, nn = S.nn, cnt = 1 << (nk + nn);
           float2* dst = reinterpret_cast<float2*>(sBf + S.boff0);
-          for (int i = tid; i < cnt; i += 256) dst[i] = B[tab.boff[S.voff0 + i]];
+          for (int i = tid; i < cnt; i += 256) {
+            const int n = i >> nk, k = i & ((1 << nk) - 1);
+            dst[i] = B[chain_off(k, S.kB, 0, nk) + chain_off(n, S.nB, 0, nn)];
+          }
         }
       }
       restage = false;
@@ -764,7 +752,7 @@ k_chain(ChainArgs) {
     }
     for (int q = 0; q < nsteps; ++q) {
       karg_step& S = g.st[q];
-      chain_step<LIGHT>(S, buf, sBf + S.boff0, tab.rhi[q], g.split != 0);
+      chain_step<CLS>(S, buf, sBf + S.boff0, g.split != 0);
       __syncthreads();
     }
     // store the output tile

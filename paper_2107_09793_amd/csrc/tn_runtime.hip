@@ -384,17 +384,26 @@ tn_status run_chain(const Ctx& c, const tn::ChainGroup& g, uint64_t outer_val,
   if (probe && !probe->done)
     for (int k = g.first; k <= g.last; ++k) timed |= probe->step == k;
   if (timed) TN_HIP_CHECK(hipEventRecord(probe->start, c.st));
-  bool heavy = false;
-  for (int q = 0; q < a.nsteps; ++q)
+  // kernel build: small shapes with staged operands that leave room for 4
+  // workgroups per CU (LDS: 32 KiB tile + staging <= 40 KiB), else the
+  // prefetching build unless a split-BF16 step needs the full one
+  bool heavy = false, small = true;
+  for (int q = 0; q < a.nsteps; ++q) {
     heavy |= tn::chain_needs_heavy(a.st[q].nk, a.st[q].mfma != 0, a.split != 0);
+    small &= tnk::chain_small_step(a.st[q].nk, a.st[q].nn, a.st[q].mfma != 0);
+  }
+  const size_t dyn = std::max<size_t>(16, (size_t)a.b_total * sizeof(float));
+  small &= (sizeof(float2) << 12) + dyn <= 40u * 1024u;
   if (g.tile_bits <= 10)
-    hipLaunchKernelGGL((tnk::k_chain<10, false>), dim3(grid), dim3(256), 0, c.st, a);
+    hipLaunchKernelGGL((tnk::k_chain<10, 0>), dim3(grid), dim3(256), dyn, c.st, a);
   else if (g.tile_bits == 11)
-    hipLaunchKernelGGL((tnk::k_chain<11, false>), dim3(grid), dim3(256), 0, c.st, a);
+    hipLaunchKernelGGL((tnk::k_chain<11, 0>), dim3(grid), dim3(256), dyn, c.st, a);
+  else if (small)
+    hipLaunchKernelGGL((tnk::k_chain<12, 2>), dim3(grid), dim3(256), dyn, c.st, a);
   else if (heavy)
-    hipLaunchKernelGGL((tnk::k_chain<12, false>), dim3(grid), dim3(256), 0, c.st, a);
+    hipLaunchKernelGGL((tnk::k_chain<12, 0>), dim3(grid), dim3(256), dyn, c.st, a);
   else
-    hipLaunchKernelGGL((tnk::k_chain<12, true>), dim3(grid), dim3(256), 0, c.st, a);
+    hipLaunchKernelGGL((tnk::k_chain<12, 1>), dim3(grid), dim3(256), dyn, c.st, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(TN_E_HIP, std::string("chain launch: ") + hipGetErrorString(e));
   if (timed) {
