@@ -77,6 +77,9 @@ typedef enum { TN_OUT_SUM = 0, TN_OUT_PER_SLICE = 1 } tn_out_mode;
 #define TN_FLAG_NO_CHAIN 8u       /* run every step of a chain (consecutive stream
                                      steps on one running tensor) as its own launch
                                      instead of one fused launch per chain           */
+#define TN_FLAG_CHAIN_NO_SINGLE 128u /* a chainable step with no chainable
+                                     neighbour runs on its own kernel instead of as
+                                     a one-step chain                                */
 #define TN_N_GEMM_CONFIGS 6       /* tile configurations per precision              */
 
 typedef struct {

@@ -23,6 +23,7 @@ TN_FLAG_NO_CHAIN = 8
 TN_FLAG_PERSISTENT = 16
 TN_FLAG_CHAIN_VALU = 32
 TN_FLAG_CHAIN_STEPWISE = 64
+TN_FLAG_CHAIN_NO_SINGLE = 128
 KIND_NAMES = {0: "simple", 1: "splitk", 2: "stream", 3: "gemm"}
 
 I8x48 = ctypes.c_int8 * 48
@@ -179,7 +180,7 @@ class Plan:
     def __init__(self, labels, dims, open_ids, path, sliced=(), precision="c64",
                  max_resident_bits=-1, workspace_limit="auto", no_reuse=False, simple=False,
                  gemm_config=-1, tune="default", persistent=False, chains=True,
-                 chain_mfma=True, chain_fused=True):
+                 chain_mfma=True, chain_fused=True, chain_single=True):
         n_index = (max(dims) + 1) if isinstance(dims, dict) else len(dims)
         dim_arr = [dims[i] for i in range(n_index)]
         ranks, r_p = _i32([len(l) for l in labels])
@@ -197,7 +198,8 @@ class Plan:
             (TN_FLAG_SIMPLE_KERNELS if simple else 0) | \
             (TN_FLAG_PERSISTENT if persistent else 0) | (0 if chains else TN_FLAG_NO_CHAIN) | \
             (0 if chain_mfma else TN_FLAG_CHAIN_VALU) | \
-            (0 if chain_fused else TN_FLAG_CHAIN_STEPWISE)
+            (0 if chain_fused else TN_FLAG_CHAIN_STEPWISE) | \
+            (0 if chain_single else TN_FLAG_CHAIN_NO_SINGLE)
         opts.gemm_config = gemm_config
         entries = load_tune_table() if tune == "default" else (tune or [])
         tarr, t_p = _i32([x for e in entries for x in e] or [0])

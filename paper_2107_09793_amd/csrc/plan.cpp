@@ -606,7 +606,12 @@ static void schedule_pass(Plan& p) {
         g = cand;
         ++j;
       }
-      if (j > k) {
+      if (j == k && !(p.flags & 128u) && build_chain(p, lay, sbits, k, k, cand)) {   // TN_FLAG_CHAIN_NO_SINGLE
+        // a lone step runs on the chain kernel too: its tile walk streams
+        // the large operand with the small one staged once per workgroup
+        g = cand;
+      }
+      if (j > k || g.st.size() == 1) {
         for (int q = k; q <= j; ++q) p.steps[q].chain = (int32_t)p.chains.size();
         p.chains.push_back(g);
       }

@@ -186,7 +186,7 @@ def test_cpu_execution_of_fused_chains_matches_oracle(cfg):
     assert any(ch["pas_in"] for ch in chains)
     steps = pl.steps()
     for ch in chains:
-        assert 2 <= len(ch["st"]) <= 8 and ch["tile_bits"] <= 12
+        assert 1 <= len(ch["st"]) <= 8 and ch["tile_bits"] <= 12
         for k in range(ch["first"], ch["last"]):
             assert steps[k + 1]["a"] == pl.n_tensors + k and steps[k]["c_offset"] == -1
         # staged small operands: 4 floats per entry on the matrix cores (k
@@ -206,6 +206,13 @@ def test_cpu_execution_of_fused_chains_matches_oracle(cfg):
     assert all(s["c_offset"] >= 0 for s in stepwise.steps())
     got2, _ = execute(stepwise, tn.tensors)
     assert np.allclose(got2, ref, rtol=1e-12, atol=1e-13 * np.max(np.abs(ref)))
+    # lone chainable steps run as one-step chains unless switched off
+    multi = Plan.from_network(tn, p, sl, chain_single=False)
+    mch = multi.chains()
+    assert all(len(ch["st"]) >= 2 for ch in mch)
+    assert len(mch) == sum(len(ch["st"]) >= 2 for ch in chains)
+    got3, _ = execute(multi, tn.tensors)
+    assert np.allclose(got3, ref, rtol=1e-12, atol=1e-13 * np.max(np.abs(ref)))
     unfused = Plan.from_network(tn, p, sl, persistent=False, chains=False)
     assert unfused.info()["n_chains"] == 0
     assert unfused.info()["n_launches"] - info["n_launches"] == sum(
