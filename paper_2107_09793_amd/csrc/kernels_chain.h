@@ -529,11 +529,12 @@ __device__ __forceinline__ void chain_rows_mfma_sb(karg_step& S, float2* buf, co
 //  1  no split-BF16 matrix-core step with 2^nk >= 32 (the only shapes that
 //     need far more registers than the rest): room to prefetch the next tile;
 //  2  small shapes only (chain_small_step): few enough registers for 4 waves
-//     per SIMD, used when the chain's staged operands also leave room for 4
+//     per SIMD (matrix steps up to 2^4 x 2^4, vector steps up to 2^3 x 2^4
+//     and 2^4 x 2^2), used when the chain's staged operands also leave room for 4
 //     workgroups per CU.
-// The host picks the build from the chain's steps (chain_build_class).
+// The launcher picks the build from the chain's steps and staging size.
 __host__ __device__ constexpr bool chain_small_step(int nk, int nn, bool mfma) {
-  return mfma ? (nk <= 4 && nn <= 4) : (nk <= 3 && nn <= 4);
+  return mfma ? (nk <= 4 && nn <= 4) : (nk <= 3 && nn <= 4) || (nk == 4 && nn <= 2);
 }
 
 template <int CLS>
@@ -569,8 +570,9 @@ __device__ __forceinline__ void chain_step(karg_step& S, float2* buf, const floa
 #define TNK_CHAIN_ROW(A) \
   TNK_CHAIN_CASE(A, 0) TNK_CHAIN_CASE(A, 1) TNK_CHAIN_CASE(A, 2) TNK_CHAIN_CASE(A, 3) TNK_CHAIN_CASE(A, 4)
   TNK_CHAIN_ROW(0) TNK_CHAIN_ROW(1) TNK_CHAIN_ROW(2) TNK_CHAIN_ROW(3)
+  TNK_CHAIN_CASE(4, 0) TNK_CHAIN_CASE(4, 1) TNK_CHAIN_CASE(4, 2)
   if constexpr (!SMALL) {
-    TNK_CHAIN_ROW(4)
+    TNK_CHAIN_CASE(4, 3) TNK_CHAIN_CASE(4, 4)
   }
 #undef TNK_CHAIN_ROW
 #undef TNK_CHAIN_CASE
