@@ -80,7 +80,7 @@ typedef enum { TN_OUT_SUM = 0, TN_OUT_PER_SLICE = 1 } tn_out_mode;
 #define TN_FLAG_CHAIN_NO_SINGLE 128u /* a chainable step with no chainable
                                      neighbour runs on its own kernel instead of as
                                      a one-step chain                                */
-#define TN_N_GEMM_CONFIGS 7       /* tile configurations per precision              */
+#define TN_N_GEMM_CONFIGS 8       /* tile configurations per precision              */
 
 typedef struct {
   int32_t precision;          /* tn_precision                                       */

@@ -173,7 +173,7 @@ int32_t choose_kind(int nb, int nm, int nn, int nk, uint32_t flags, int32_t* chu
                     int64_t* scratch);
 
 // GEMM tile configuration for a step shape: forced, tune table, or rule.
-constexpr int kNumGemmConfigs = 7;
+constexpr int kNumGemmConfigs = 8;
 int32_t choose_tile(const Plan& p, int nm, int nn, int nk);
 
 // Builds the plan; returns empty string on success, else an error message.

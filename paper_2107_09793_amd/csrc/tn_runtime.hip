@@ -206,6 +206,7 @@ tn_status launch_gemm(const tnk::StepArgs& a, int32_t precision, int32_t tile, h
     case 4: return launch_gemm_cfg<2, 2, 4, 2, 4>(a, precision, st);   // 256 x 64
     case 5: return launch_gemm_cfg<2, 2, 2, 2, 5>(a, precision, st);   // 128 x 64, k tile 32
     case 6: return launch_gemm_cfg<4, 1, 1, 2, 3>(a, precision, st);   // 128 x 32, k tile 8
+    case 7: return launch_gemm_cfg<4, 1, 1, 1, 4>(a, precision, st);   // 128 x 16
     default: return fail(TN_E_INVALID, "unknown GEMM tile configuration");
   }
 }

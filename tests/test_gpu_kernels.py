@@ -98,7 +98,7 @@ def test_gemm_deterministic_run_to_run():
 
 
 @pytest.mark.parametrize("precision", ["c64", "split_bf16"])
-@pytest.mark.parametrize("cfg", range(7))
+@pytest.mark.parametrize("cfg", range(8))
 def test_every_gemm_tile_config(cfg, precision):
     """Each compiled tile configuration, forced on a full and a partial tile shape."""
     if not torch.cuda.is_available():
