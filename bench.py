@@ -150,23 +150,25 @@ def kernel_sha(kind):
 def measured_traffic(workload, unit, precision):
     """HBM bytes per launch of the dominant launch from the committed counter
     summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when there is
-    no summary for this workload and precision, it is for another launch, or
-    the kernel source changed since the counters were taken."""
+    no summary for this workload and precision, none of its entries is this
+    launch, or the kernel source changed since the counters were taken."""
     import re
     path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}_{precision}.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
-    m_b = re.search(r"traffic_bytes:\s*([0-9.eE+]+)", txt)
     m_h = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
-    m_s = re.search(r"launch:\s*(\w+) steps ([0-9,]+)", txt)
-    if not (m_b and m_h and m_s):
+    if not m_h or kernel_sha(unit["kind"]) != m_h.group(1):
         return None
-    kind = m_s.group(1)
-    steps = [int(x) for x in m_s.group(2).split(",")]
-    if kind != unit["kind"] or kernel_sha(kind) != m_h.group(1) or steps != unit["steps"]:
-        return None
-    return float(m_b.group(1))
+    launch = None
+    for line in txt.splitlines():
+        m_s = re.match(r"launch:\s*(\w+) steps ([0-9,]+)", line)
+        if m_s:
+            launch = (m_s.group(1), [int(x) for x in m_s.group(2).split(",")])
+        m_b = re.match(r"traffic_bytes:\s*([0-9.eE+]+)", line)
+        if m_b and launch == (unit["kind"], unit["steps"]):
+            return float(m_b.group(1))
+    return None
 
 
 def oracle_cores():
