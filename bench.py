@@ -351,7 +351,7 @@ def main():
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): slices are independent, "
               "so the multi-GPU layout is one slice range per GPU plus one all-reduce of the "
-              "float64 partial sums; this build measures the single-GPU share.", file=sys.stderr)
+              "float64 partial sums; this benchmark measures the single-GPU share.", file=sys.stderr)
         sys.exit(2)
     if args.steps is None:
         args.steps = 3 if args.workload == "precision" else 10

@@ -49,7 +49,7 @@ typedef struct tn_plan_s* tn_plan_t;
 typedef enum {
   TN_OK = 0,
   TN_E_INVALID = 1,      /* malformed network, path, slice list or argument   */
-  TN_E_UNSUPPORTED = 2,  /* valid input outside what this build supports      */
+  TN_E_UNSUPPORTED = 2,  /* valid input outside what the library supports    */
   TN_E_WORKSPACE = 3,    /* workspace smaller than tn_plan_info.workspace_bytes */
   TN_E_OOM = 4,          /* host allocation failed                            */
   TN_E_HIP = 5           /* a HIP runtime call or kernel launch failed        */
