@@ -103,3 +103,21 @@ def test_chain_split_bf16(cfg):
     ref = np.asarray(ref).reshape(got.shape)
     rms = np.sqrt(np.mean(np.abs(ref) ** 2))
     assert np.max(np.abs(got - ref)) <= 1e-3 * rms
+
+
+@pytest.mark.parametrize("cfg", [(7, 4, 4, 14, 32, 2), (9, 4, 4, 10, 16, 3)])
+def test_one_step_chains_bitwise(cfg):
+    """A lone stream step run as a one-step chain on the vector units forms
+    every value by the same complex FMAs in the same order as the stream
+    kernel: identical results with and without one-step chains."""
+    from paper_2107_09793_amd import Plan
+    dev = _dev()
+    tn, p, sl = _batch_net(*cfg)
+    leaves = [torch.from_numpy(t.astype(np.complex64)).to(dev) for t in tn.tensors]
+    single = Plan.from_network(tn, p, sl, chain_mfma=False)
+    multi = Plan.from_network(tn, p, sl, chain_mfma=False, chain_single=False)
+    assert any(ch["first"] == ch["last"] for ch in single.chains())
+    assert all(ch["first"] < ch["last"] for ch in multi.chains())
+    a = single.contract(leaves, per_slice=True).cpu().numpy()
+    b = multi.contract(leaves, per_slice=True).cpu().numpy()
+    assert np.array_equal(a, b)
