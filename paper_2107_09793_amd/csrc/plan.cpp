@@ -407,6 +407,9 @@ int32_t choose_kind(int nb, int nm, int nn, int nk, uint32_t flags, int32_t* chu
   if (flags & 2u) return KIND_SIMPLE;
   if (nk <= 4 && nn <= 4 && nb <= 12) return KIND_STREAM;
   if (nm >= 5 && nn >= 3 && nk >= 3) return KIND_GEMM;
+  // many rows against a few columns and many summed values: the GEMM
+  // kernel with its narrowest tile (partial columns) streams the rows
+  if (nm >= 12 && nn >= 1 && nk >= 5) return KIND_GEMM;
   return KIND_SIMPLE;
 }
 
@@ -425,7 +428,7 @@ int32_t choose_tile(const Plan& p, int nm, int nn, int nk) {
   if (best >= 0) return best;
   if (nn >= 6) return 0;   // 128 x 64
   if (nn == 5) return 1;   // 128 x 32
-  return 2;                // 256 x 16
+  return 7;                // 128 x 16
 }
 
 // Build schedule for a given outer set; fills steps, sched, memory, stats.

@@ -47,6 +47,8 @@ CASES = [
     (2, 8, 4, 7, 0, "gemm"),       # 256x16 tiles
     (0, 5, 3, 5, 0, "gemm"),       # partial row and column tiles
     (0, 5, 6, 3, 0, "gemm"),       # partial row and k tiles (operands swap roles)
+    (0, 12, 2, 6, 0, "gemm"),      # many rows, 4 columns: the narrowest tile, partial columns
+    (1, 12, 1, 5, 0, "gemm"),
     (0, 6, 9, 9, 1, "gemm"),       # dim-4 rows
     (0, 12, 3, 2, 0, "stream"),
     (2, 10, 2, 4, 1, "stream"),
