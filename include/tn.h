@@ -129,6 +129,11 @@ typedef struct {
   int8_t outer_slicebit[48];
   int32_t n_chains;               /* fused chains of stream steps (one launch each) */
   int32_t n_segments;             /* persistent launches of small steps             */
+  int64_t segment_table_bytes;    /* control tables of the persistent segments      */
+  int64_t segment_table_offset;   /* their byte offset inside the workspace         */
+  int32_t n_phase0;               /* schedule positions 0 .. n_phase0-1 run once
+                                     (they depend on no outer sliced index)         */
+  int32_t reserved_info;
 } tn_plan_info;
 
 /* One step as scheduled (tests, benchmarks, autotuning). */
@@ -246,6 +251,45 @@ tn_status tn_contract_probe(tn_plan_t plan, const void* const* leaves, const int
                             int64_t n_slice_ids, int32_t out_mode, void* out, void* ws,
                             size_t ws_bytes, void* stream, int32_t probe_step, void* ev_start,
                             void* ev_stop);
+
+/*
+ * Execution order of the steps: order[i] is the step run at position i
+ * (n >= n_steps entries).  Positions 0 .. info.n_phase0-1 run once per call,
+ * the rest once per outer iteration.  Needs no GPU.
+ */
+tn_status tn_plan_schedule(tn_plan_t plan, int32_t* order, int32_t n);
+
+/*
+ * Control tables of the persistent segments (TN_FLAG_PERSISTENT) exactly as
+ * tn_contract copies them to ws + info.segment_table_offset for these leaf
+ * and workspace pointers (which are only stored, never dereferenced: needs no
+ * GPU).  blob receives info.segment_table_bytes bytes:
+ *   bytes 0..255          header; int32 word 0 is the error word that every
+ *                         segment launch sets to 1 when a wait timed out;
+ *   per (segment, execution) lay[i] gives the byte offsets (from the start
+ *   of blob) of
+ *     off_desc   n_steps descriptors of 272 bytes: A, B, C device pointers,
+ *                int32 nb, nm, nn, nk, n_items, item0, dep0, dep1 (segment
+ *                positions of producer steps inside the segment, -1 = none),
+ *                then 24-entry int8 log2-stride arrays sA_b, sB_b, sC_b,
+ *                sA_m, sC_m, sB_n, sC_n, sA_k, sB_k;
+ *     off_items  n_items int32: the segment position of each work item
+ *                (work items are claimed in this order);
+ *     off_ctr    zeroed int32 counters: word 0 the ticket, word 32*(1+s)
+ *                the completed items of segment position s.
+ * lay[max_lay] receives one entry per (segment, execution), *n_lay their
+ * number; TN_E_INVALID if blob_bytes or max_lay is too small.
+ */
+typedef struct {
+  int32_t segment, execution;  /* segment index, outer iteration (0 for phase 0) */
+  int32_t n_steps, n_items;
+  int32_t first_pos;           /* schedule position of the segment's first step  */
+  int32_t reserved;
+  int64_t off_desc, off_items, off_ctr;
+} tn_segment_layout;
+tn_status tn_plan_segment_tables(tn_plan_t plan, const void* const* leaves, void* ws,
+                                 void* blob, int64_t blob_bytes, tn_segment_layout* lay,
+                                 int32_t max_lay, int32_t* n_lay);
 
 /* Chain ``i`` (0 <= i < info.n_chains) of the plan. */
 tn_status tn_plan_chain(tn_plan_t plan, int32_t i, tn_chain_info* out);

@@ -11,7 +11,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libtnmi.so")
+# TNMI_LIB_PATH selects another build of the same library (the host-sanitizer
+# build that the CPU test suite runs the plan tests against)
+LIB_PATH = os.environ.get("TNMI_LIB_PATH") or os.path.join(_HERE, "libtnmi.so")
 
 TN_OK, TN_E_INVALID, TN_E_UNSUPPORTED, TN_E_WORKSPACE, TN_E_OOM, TN_E_HIP = range(6)
 TN_C64, TN_SPLIT_BF16 = 0, 1
@@ -48,7 +50,9 @@ class PlanInfo(ctypes.Structure):
             "bytes_min_exec")] + \
         [(n, I8x48) for n in ("root_open_log2", "root_res_log2", "res_slicebit",
                               "outer_slicebit")] + \
-        [("n_chains", ctypes.c_int32), ("n_segments", ctypes.c_int32)]
+        [("n_chains", ctypes.c_int32), ("n_segments", ctypes.c_int32),
+         ("segment_table_bytes", ctypes.c_int64), ("segment_table_offset", ctypes.c_int64),
+         ("n_phase0", ctypes.c_int32), ("reserved_info", ctypes.c_int32)]
 
 
 class StepInfo(ctypes.Structure):
@@ -75,9 +79,15 @@ class ChainInfo(ctypes.Structure):
         [("st", ChainStepInfo * 8)]
 
 
+class SegmentLayout(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("segment", "execution", "n_steps", "n_items",
+                                              "first_pos", "reserved")] + \
+        [(n, ctypes.c_int64) for n in ("off_desc", "off_items", "off_ctr")]
+
+
 EXPORTS = ("tn_plan_create", "tn_plan_query", "tn_plan_step", "tn_contract",
            "tn_contract_probe", "tn_contract_backward", "tn_plan_destroy", "tn_last_error",
-           "tn_permute", "tn_plan_chain")
+           "tn_permute", "tn_plan_chain", "tn_plan_schedule", "tn_plan_segment_tables")
 
 _lib = None
 
@@ -108,6 +118,12 @@ def lib():
         L.tn_contract_backward.restype = ctypes.c_int
         L.tn_contract_backward.argtypes = [P, ctypes.POINTER(P), P, ctypes.POINTER(P), P,
                                            ctypes.c_size_t, P]
+        L.tn_plan_schedule.restype = ctypes.c_int
+        L.tn_plan_schedule.argtypes = [P, i32p, ctypes.c_int32]
+        L.tn_plan_segment_tables.restype = ctypes.c_int
+        L.tn_plan_segment_tables.argtypes = [P, ctypes.POINTER(P), P, P, ctypes.c_int64,
+                                             ctypes.POINTER(SegmentLayout), ctypes.c_int32,
+                                             ctypes.POINTER(ctypes.c_int32)]
         L.tn_plan_chain.restype = ctypes.c_int
         L.tn_plan_chain.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ChainInfo)]
         L.tn_plan_destroy.restype = None
@@ -279,6 +295,29 @@ class Plan:
 
     def chains(self):
         return [self.chain(i) for i in range(self.info()["n_chains"])]
+
+    def schedule(self):
+        """Step indices in execution order (``tn_plan_schedule``)."""
+        arr = (ctypes.c_int32 * max(self.n_tensors - 1, 1))()
+        _check(lib().tn_plan_schedule(self._h, arr, len(arr)))
+        return list(arr)[:self.n_tensors - 1]
+
+    def segment_tables(self, leaf_ptrs, ws_ptr):
+        """Persistent-segment control tables for the given (integer) leaf and
+        workspace addresses (``tn_plan_segment_tables``): (bytes, layouts)."""
+        inf = self.info()
+        nbytes = int(inf["segment_table_bytes"])
+        blob = (ctypes.c_char * max(nbytes, 1))()
+        arr = (ctypes.c_void_p * self.n_tensors)(*leaf_ptrs)
+        n = ctypes.c_int32()
+        lay = (SegmentLayout * 4096)()
+        _check(lib().tn_plan_segment_tables(self._h, arr, ctypes.c_void_p(ws_ptr), blob, nbytes,
+                                            lay, len(lay), ctypes.byref(n)))
+        out = []
+        for i in range(n.value):
+            L = lay[i]
+            out.append({k: getattr(L, k) for k, _ in SegmentLayout._fields_})
+        return bytes(blob)[:nbytes], out
 
     def release_workspace(self):
         """Drop the cached device workspaces (allocated again on next use)."""

@@ -38,6 +38,9 @@ struct GemmArgs {
   // one class keep their class order.
   uint32_t a_mask, b_mask;
   int32_t xcd_remap;
+  // logical tile of workgroup 0: steps with more tiles than one dispatch can
+  // hold (2^32 work-items) run as several launches over consecutive ranges
+  uint64_t tile0;
 };
 
 template <int V>
@@ -173,7 +176,7 @@ struct GemmCommon {
     int lmt = p.nm > LM ? p.nm - LM : 0;
     ntiles = 1ull << (p.nb + lmt + lnt);
     remap = g.xcd_remap;
-    tile = blockIdx.x;
+    tile = g.tile0 + blockIdx.x;
   }
 
   __device__ __forceinline__ void set_tile(const StepArgs& p, const Strides& S, uint64_t t) {
@@ -245,7 +248,7 @@ __device__ __forceinline__ void gemm_tiles(const StepArgs& p, const Strides& S,
                                            GemmCommon<MT, NT, KT, OffT>& c,
                                            const GemmTables<MT, NT, KT>& tab, Ops& ops) {
   using GC = GemmCommon<MT, NT, KT, OffT>;
-  const uint64_t tile = blockIdx.x;
+  const uint64_t tile = c.tile;
   if (tile >= c.ntiles) return;
   float2 ra[GC::AE], rb[GC::BE];
   floatx16 acc[WM][WN];

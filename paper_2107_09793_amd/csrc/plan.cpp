@@ -431,6 +431,19 @@ int32_t choose_tile(const Plan& p, int nm, int nn, int nk) {
   return 7;                // 128 x 16
 }
 
+// Kernel launches of one execution of a step: split-k runs two kernels; a
+// GEMM step runs one launch per 2^23 output tiles (a dispatch holds fewer
+// than 2^32 work-items of 256-thread workgroups).
+static int32_t step_launches(const StepDesc& S) {
+  if (S.kind == KIND_SPLITK) return 2;
+  if (S.kind != KIND_GEMM || S.tile < 0 || S.tile >= kNumGemmConfigs) return 1;
+  static const int lm[kNumGemmConfigs] = {7, 7, 8, 7, 8, 7, 7, 7};   // log2 tile rows
+  static const int ln[kNumGemmConfigs] = {6, 5, 4, 7, 6, 6, 5, 4};   // log2 tile columns
+  const int t = (int)S.bA.size() + std::max(0, (int)S.mA.size() - lm[S.tile]) +
+                std::max(0, (int)S.nB.size() - ln[S.tile]);
+  return t > 23 ? 1 << std::min(t - 23, 24) : 1;
+}
+
 // Build schedule for a given outer set; fills steps, sched, memory, stats.
 static void schedule_pass(Plan& p);
 
@@ -767,15 +780,15 @@ static void schedule_pass(Plan& p) {
     double ec = std::ldexp(1.0, (int)p.node_ebits[S.c].size());
     p.bytes_min_exec += mult * 8.0 * (ea + eb + ec);
     p.max_log2_res = std::max(p.max_log2_res, (int32_t)p.node_ebits[S.c].size());
-    int l = (S.kind == KIND_SPLITK) ? 2 : 1;
-    (S.phase ? launches1 : launches0) += l;
+    (S.phase ? launches1 : launches0) += step_launches(S);
   }
   p.n_launches = launches0 + (int32_t)iters * (launches1 + 1) + 1;
   int64_t ctrl = align_up((int64_t)4 << p.resident_bits, 256);
   p.ctrl_bytes = ctrl;
-  // persistent segments: one copy per (segment, execution) of descriptors,
-  // item tables and counters
-  int64_t pb = 0;
+  // persistent segments: a 256-byte header (the error word every segment
+  // launch reports timed-out waits into), then one copy per (segment,
+  // execution) of descriptors, item tables and counters
+  int64_t pb = p.segments.empty() ? 0 : 256;
   for (const Segment& g : p.segments) {
     int64_t len = g.end - g.begin;
     int64_t one = align_up(len * kSmallStepBytes, 256) + align_up((int64_t)4 * g.n_items, 256) +
@@ -784,11 +797,11 @@ static void schedule_pass(Plan& p) {
   }
   p.persist_bytes = pb;
   p.workspace_bytes = align_up(p.arena_bytes, 256) + align_up(p.scratch_bytes, 256) + ctrl + pb;
-  // launches: persistent segments replace their steps' launches (plus a fill)
+  // launches: one persistent launch replaces its segment's step launches
   for (const Segment& g : p.segments) {
     int32_t saved = 0;
-    for (int q = g.begin; q < g.end; ++q) saved += p.steps[p.sched[q]].kind == KIND_SPLITK ? 2 : 1;
-    int32_t d = saved - 2;
+    for (int q = g.begin; q < g.end; ++q) saved += step_launches(p.steps[p.sched[q]]);
+    int32_t d = saved - 1;
     p.n_launches -= g.phase ? (int32_t)iters * d : d;
   }
   // chains: one launch for all their steps (unless launched step by step)

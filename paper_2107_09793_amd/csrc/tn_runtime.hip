@@ -165,9 +165,18 @@ int64_t max_tile_offset(int L1, const int8_t* s1, int n1, int L2, const int8_t* 
   return m;
 }
 
+// One workgroup of 256 threads per tile.  A dispatch holds fewer than 2^32
+// work-items, so steps with more than 2^23 tiles run as several launches,
+// each over the next range of logical tiles.
+constexpr uint64_t kMaxTilesPerLaunch = 1ull << 23;
 template <auto Kernel>
-void launch_tiles(uint64_t ntiles, const tnk::GemmArgs& g, hipStream_t st) {
-  hipLaunchKernelGGL(Kernel, dim3((unsigned)ntiles), dim3(256), 0, st, g);
+void launch_tiles(uint64_t ntiles, const tnk::GemmArgs& g0, hipStream_t st) {
+  tnk::GemmArgs g = g0;
+  for (uint64_t t0 = 0; t0 < ntiles; t0 += kMaxTilesPerLaunch) {
+    g.tile0 = t0;
+    const uint64_t n = std::min(ntiles - t0, kMaxTilesPerLaunch);
+    hipLaunchKernelGGL(Kernel, dim3((unsigned)n), dim3(256), 0, st, g);
+  }
 }
 
 template <int WVM, int WVN, int WM, int WN, int LK>
@@ -183,7 +192,6 @@ tn_status launch_gemm_cfg(const tnk::StepArgs& a, int32_t precision, hipStream_t
   g.b_mask = tile_mask(LN, a.sB_n, a.nn, lk, a.sB_k, a.nk);
   int lmt = a.nm > LM ? a.nm - LM : 0, lnt = a.nn > LN ? a.nn - LN : 0;
   uint64_t ntiles = 1ull << (a.nb + lmt + lnt);
-  if (ntiles > 0xFFFFFFFFull) return fail(TN_E_UNSUPPORTED, "too many GEMM tiles");
   g.xcd_remap = ntiles >= 64 ? 1 : 0;
   const bool small = max_tile_offset(LM, a.sA_m, a.nm, lk, a.sA_k, a.nk) < (1ll << 31) &&
                      max_tile_offset(LN, a.sB_n, a.nn, lk, a.sB_k, a.nk) < (1ll << 31);
@@ -417,9 +425,11 @@ tn_status run_chain(const Ctx& c, const tn::ChainGroup& g, uint64_t outer_val,
 
 }  // namespace
 
-// Control region of the persistent segments: for every (segment, execution)
-// the device descriptors, the item -> step table and zeroed counters, built on
-// the host and copied with one transfer at the start of tn_contract.
+// Control region of the persistent segments: a 256-byte header whose first
+// word collects timed-out waits of every segment launch, then for every
+// (segment, execution) the device descriptors, the item -> step table and
+// zeroed counters, built on the host and copied with one transfer at the
+// start of tn_contract.
 struct SegLayout {
   int64_t off_desc, off_items, off_ctr;
 };
@@ -435,7 +445,7 @@ static void build_persist_blob(const Ctx& c, std::vector<char>& blob,
   lay.assign(p.segments.size(), {});
   std::vector<int32_t> pos_of(p.steps.size(), -1);
   for (size_t q = 0; q < p.sched.size(); ++q) pos_of[p.sched[q]] = (int32_t)q;
-  int64_t off = 0;
+  int64_t off = p.segments.empty() ? 0 : 256;   // header: error word
   for (size_t gi = 0; gi < p.segments.size(); ++gi) {
     const tn::Segment& g = p.segments[gi];
     const int len = g.end - g.begin;
@@ -492,11 +502,23 @@ static tn_status launch_segment(const Ctx& c, const tn::Segment& g, const SegLay
   hipLaunchKernelGGL(tnk::k_persistent, dim3(grid), dim3(256), 0, c.st,
                      reinterpret_cast<const tnk::SmallStep*>(pbase + L.off_desc),
                      reinterpret_cast<const int32_t*>(pbase + L.off_items), g.n_items, ctr,
-                     ctr + tnk::kCtrStride * (len + 1));
+                     reinterpret_cast<int32_t*>(pbase));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(TN_E_HIP, std::string("persistent launch: ") + hipGetErrorString(e));
   return TN_OK;
 }
+
+// Keeps a host buffer that a queued host-to-device copy reads from alive
+// until the stream has passed that copy: on every exit from the call that
+// queued it, the stream is synchronised before the buffer is released.
+struct StagedUpload {
+  std::vector<char> buf;
+  hipStream_t st = nullptr;
+  bool queued = false;
+  ~StagedUpload() {
+    if (queued) (void)hipStreamSynchronize(st);
+  }
+};
 
 static tn_status contract_impl(tn_plan_t plan, const void* const* leaves,
                                const int64_t* slice_ids, int64_t n_slice_ids, int32_t out_mode,
@@ -572,6 +594,9 @@ tn_status tn_plan_query(tn_plan_t plan, tn_plan_info* out) {
   for (int j = 0; j < p.outer_bits; ++j) out->outer_slicebit[j] = (int8_t)p.outer_slicebit[j];
   out->n_chains = (int32_t)p.chains.size();
   out->n_segments = (int32_t)p.segments.size();
+  out->segment_table_bytes = p.persist_bytes;
+  out->segment_table_offset = al256(p.arena_bytes) + al256(p.scratch_bytes) + p.ctrl_bytes;
+  out->n_phase0 = p.n_phase0;
   return TN_OK;
 }
 
@@ -649,6 +674,51 @@ tn_status tn_plan_chain(tn_plan_t plan, int32_t i, tn_chain_info* out) {
   return TN_OK;
 }
 
+tn_status tn_plan_segment_tables(tn_plan_t plan, const void* const* leaves, void* ws,
+                                 void* blob, int64_t blob_bytes, tn_segment_layout* lay,
+                                 int32_t max_lay, int32_t* n_lay) {
+  if (!plan || !leaves || !blob || !n_lay) return fail(TN_E_INVALID, "NULL argument");
+  const tn::Plan& p = plan->p;
+  if (blob_bytes < p.persist_bytes) return fail(TN_E_INVALID, "blob smaller than the tables");
+  for (int t = 0; t < p.n_tensors; ++t)
+    if (!leaves[t]) return fail(TN_E_INVALID, "NULL leaf pointer");
+  try {
+    Ctx c{p, leaves, static_cast<char*>(ws), nullptr, nullptr};
+    std::vector<char> b;
+    std::vector<std::vector<SegLayout>> L;
+    build_persist_blob(c, b, L);
+    if (!b.empty()) memcpy(blob, b.data(), b.size());
+    int32_t k = 0;
+    for (size_t gi = 0; gi < L.size(); ++gi)
+      for (size_t e = 0; e < L[gi].size(); ++e, ++k) {
+        if (k >= max_lay || !lay) continue;
+        tn_segment_layout& o = lay[k];
+        memset(&o, 0, sizeof o);
+        o.segment = (int32_t)gi;
+        o.execution = (int32_t)e;
+        o.n_steps = p.segments[gi].end - p.segments[gi].begin;
+        o.n_items = p.segments[gi].n_items;
+        o.first_pos = p.segments[gi].begin;
+        o.off_desc = L[gi][e].off_desc;
+        o.off_items = L[gi][e].off_items;
+        o.off_ctr = L[gi][e].off_ctr;
+      }
+    *n_lay = k;
+    if (k > max_lay) return fail(TN_E_INVALID, "layout array too short");
+    return TN_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(TN_E_OOM, "host allocation failed");
+  }
+}
+
+tn_status tn_plan_schedule(tn_plan_t plan, int32_t* order, int32_t n) {
+  if (!plan || !order) return fail(TN_E_INVALID, "NULL argument");
+  const tn::Plan& p = plan->p;
+  if (n < (int32_t)p.sched.size()) return fail(TN_E_INVALID, "order array too short");
+  for (size_t i = 0; i < p.sched.size(); ++i) order[i] = p.sched[i];
+  return TN_OK;
+}
+
 tn_status tn_contract(tn_plan_t plan, const void* const* leaves, const int64_t* slice_ids,
                       int64_t n_slice_ids, int32_t out_mode, void* out, void* ws,
                       size_t ws_bytes, void* stream) {
@@ -714,11 +784,16 @@ static tn_status contract_impl(tn_plan_t plan, const void* const* leaves, const 
   std::vector<std::vector<SegLayout>> lay;
   std::vector<int32_t> seg_at(p.sched.size(), -1);
   char* pbase = c.ws + al256(p.arena_bytes) + al256(p.scratch_bytes) + p.ctrl_bytes;
+  // The tables are copied from host memory; the copy may still read the
+  // host buffer after hipMemcpyAsync returns, so the buffer lives until the
+  // stream has passed the copy (StagedUpload synchronises on every exit).
+  StagedUpload upload;
+  upload.st = st;
   if (!p.segments.empty()) {
-    std::vector<char> blob;
-    build_persist_blob(c, blob, lay);
-    // pageable source: the copy is staged before hipMemcpyAsync returns
-    TN_HIP_CHECK(hipMemcpyAsync(pbase, blob.data(), blob.size(), hipMemcpyHostToDevice, st));
+    build_persist_blob(c, upload.buf, lay);
+    TN_HIP_CHECK(hipMemcpyAsync(pbase, upload.buf.data(), upload.buf.size(),
+                                hipMemcpyHostToDevice, st));
+    upload.queued = true;
     for (size_t gi = 0; gi < p.segments.size(); ++gi) seg_at[p.segments[gi].begin] = (int32_t)gi;
   }
   auto run_range = [&](size_t from, size_t to, uint64_t it) -> tn_status {
@@ -804,6 +879,16 @@ static tn_status contract_impl(tn_plan_t plan, const void* const* leaves, const 
         TN_HIP_CHECK(hipGetLastError());
       }
     }
+  }
+  if (!p.segments.empty()) {
+    // a segment wait that timed out skipped its item's arithmetic: the
+    // result is wrong, so the call fails
+    int32_t err_word = 0;
+    TN_HIP_CHECK(hipMemcpyAsync(&err_word, pbase, sizeof err_word, hipMemcpyDeviceToHost, st));
+    TN_HIP_CHECK(hipStreamSynchronize(st));
+    upload.queued = false;
+    if (err_word != 0)
+      return fail(TN_E_HIP, "a persistent segment wait timed out; the result is invalid");
   }
   return TN_OK;
 }

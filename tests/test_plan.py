@@ -317,3 +317,25 @@ def test_outer_split_and_no_reuse_statistics():
     assert nr["cmac_exec"] == pytest.approx(full["cmac_noreuse"])
     lim = Plan.from_network(tn, p, sl, workspace_limit=full["arena_bytes"] // 3).info()
     assert lim["arena_bytes"] <= full["arena_bytes"] // 3
+
+
+def test_workspace_too_small_is_reported():
+    """TN_E_WORKSPACE before any device work: the status is returned while
+    the pointers are only checked for NULL (fake addresses are never used)."""
+    import ctypes
+    tn, p = _small_net(seed=2)
+    ts = slicing.TreeSets(tn.labels, tn.dims, tn.open, p)
+    pl = Plan.from_network(tn, p, slicing.greedy_slices(ts, n_slice=2))
+    info = pl.info()
+    L = binding.lib()
+    fake = (ctypes.c_void_p * pl.n_tensors)(*([0x1000] * pl.n_tensors))
+    for ws_bytes in (0, info["workspace_bytes"] - 1):
+        st = L.tn_contract(pl._h, fake, None, 0, binding.TN_OUT_SUM, ctypes.c_void_p(0x2000),
+                           ctypes.c_void_p(0x3000), ws_bytes, None)
+        assert st == binding.TN_E_WORKSPACE
+        assert b"workspace" in L.tn_last_error()
+    grads = (ctypes.c_void_p * pl.n_tensors)(*([0x4000] * pl.n_tensors))
+    st = L.tn_contract_backward(pl._h, fake, ctypes.c_void_p(0x2000), grads,
+                                ctypes.c_void_p(0x3000), info["workspace_backward_bytes"] - 1,
+                                None)
+    assert st == binding.TN_E_WORKSPACE
