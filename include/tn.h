@@ -228,6 +228,24 @@ tn_status tn_contract(tn_plan_t plan, const void* const* leaves, const int64_t* 
                       size_t ws_bytes, void* stream);
 
 /*
+ * tn_contract for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * workspace is the library's own file-scope device array of
+ * TN_NOALLOC_WORKSPACE_BYTES bytes (one per GPU, held until the process
+ * ends), so the caller passes only leaves and out.  Arguments and results as
+ * in tn_contract; the call itself allocates nothing.
+ * Returns TN_E_WORKSPACE when info.workspace_bytes exceeds
+ * TN_NOALLOC_WORKSPACE_BYTES.  Every call on one GPU shares that GPU's array:
+ * calls that overlap in time on one GPU (other streams, other threads) race
+ * and give wrong results; serialise them.  Nothing in the array needs to
+ * start at zero (every buffer is written before it is read).
+ */
+#define TN_NOALLOC_WORKSPACE_BYTES (64ull << 20)
+tn_status tn_contract_noalloc(tn_plan_t plan, const void* const* leaves,
+                              const int64_t* slice_ids, int64_t n_slice_ids, int32_t out_mode,
+                              void* out, void* stream);
+
+/*
  * Adjoint of tn_contract with out_mode TN_OUT_SUM over all slices.
  * grad_out: device complex128[out_elems], the gradient of a real loss with
  * respect to the output in PyTorch's convention (dL/d conj(out)).

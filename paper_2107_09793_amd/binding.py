@@ -87,7 +87,9 @@ class SegmentLayout(ctypes.Structure):
 
 EXPORTS = ("tn_plan_create", "tn_plan_query", "tn_plan_step", "tn_contract",
            "tn_contract_probe", "tn_contract_backward", "tn_plan_destroy", "tn_last_error",
-           "tn_permute", "tn_plan_chain", "tn_plan_schedule", "tn_plan_segment_tables")
+           "tn_permute", "tn_plan_chain", "tn_plan_schedule", "tn_plan_segment_tables",
+           "tn_contract_noalloc")
+NOALLOC_WORKSPACE_BYTES = 64 << 20
 
 _lib = None
 
@@ -118,6 +120,9 @@ def lib():
         L.tn_contract_backward.restype = ctypes.c_int
         L.tn_contract_backward.argtypes = [P, ctypes.POINTER(P), P, ctypes.POINTER(P), P,
                                            ctypes.c_size_t, P]
+        L.tn_contract_noalloc.restype = ctypes.c_int
+        L.tn_contract_noalloc.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_int64),
+                                          ctypes.c_int64, ctypes.c_int32, P, P]
         L.tn_plan_schedule.restype = ctypes.c_int
         L.tn_plan_schedule.argtypes = [P, i32p, ctypes.c_int32]
         L.tn_plan_segment_tables.restype = ctypes.c_int
@@ -377,6 +382,21 @@ class Plan:
                     e.record()
             _check(lib().tn_contract_probe(*args, step, ctypes.c_void_p(e0.cuda_event),
                                            ctypes.c_void_p(e1.cuda_event)))
+        return out
+
+    def contract_noalloc(self, leaves, out, slice_ids=None, per_slice=False, stream=None):
+        """``tn_contract_noalloc``: the library's own static workspace, the
+        caller's ``out`` (complex128, shaped as ``contract`` returns it)."""
+        arr, dev = self._leaf_ptrs(leaves)
+        if slice_ids is not None:
+            sids = np.ascontiguousarray(np.asarray(slice_ids, dtype=np.int64))
+            sp = sids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+            nsel = len(sids)
+        else:
+            sids, sp, nsel = None, None, 0
+        mode = TN_OUT_PER_SLICE if per_slice else TN_OUT_SUM
+        _check(lib().tn_contract_noalloc(self._h, arr, sp, nsel, mode,
+                                         ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
         return out
 
     def backward(self, leaves, grad_out, grad_leaves, stream=None):

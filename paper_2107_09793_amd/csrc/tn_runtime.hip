@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -892,6 +893,54 @@ static tn_status contract_impl(tn_plan_t plan, const void* const* leaves, const 
   }
   return TN_OK;
 }
+
+// Workspace of tn_contract_noalloc: a file-scope device array, one copy per
+// GPU the library runs on, held until the process ends.  Host code never
+// passes the array's name to a kernel or a copy: on each device its address
+// comes from hipGetSymbolAddress, taken once with that device current.
+static __device__ __align__(256) char scratch[TN_NOALLOC_WORKSPACE_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+tn_status scratch_on_current_device(void** out) {
+  int dev = -1;
+  TN_HIP_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(TN_E_UNSUPPORTED, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(TN_E_HIP, std::string("hipGetSymbolAddress(scratch) failed: ") +
+                                hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return TN_OK;
+}
+}  // namespace
+
+extern "C" {
+
+tn_status tn_contract_noalloc(tn_plan_t plan, const void* const* leaves, const int64_t* slice_ids,
+                              int64_t n_slice_ids, int32_t out_mode, void* out, void* stream) {
+  if (!plan) return fail(TN_E_INVALID, "NULL plan");
+  if (plan->p.workspace_bytes > (int64_t)TN_NOALLOC_WORKSPACE_BYTES)
+    return fail(TN_E_WORKSPACE,
+                "plan needs " + std::to_string(plan->p.workspace_bytes) +
+                    " workspace bytes; tn_contract_noalloc holds at most " +
+                    std::to_string((long long)TN_NOALLOC_WORKSPACE_BYTES));
+  void* ws = nullptr;
+  tn_status s = scratch_on_current_device(&ws);
+  if (s != TN_OK) return s;
+  return contract_impl(plan, leaves, slice_ids, n_slice_ids, out_mode, out, ws,
+                       (size_t)TN_NOALLOC_WORKSPACE_BYTES, stream, nullptr);
+}
+
+}  // extern "C"
 
 extern "C" {
 
