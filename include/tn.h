@@ -80,6 +80,9 @@ typedef enum { TN_OUT_SUM = 0, TN_OUT_PER_SLICE = 1 } tn_out_mode;
 #define TN_FLAG_CHAIN_NO_SINGLE 128u /* a chainable step with no chainable
                                      neighbour runs on its own kernel instead of as
                                      a one-step chain                                */
+#define TN_FLAG_FIT_BACKWARD 256u  /* the resident / outer split also keeps
+                                     info.workspace_backward_bytes within
+                                     workspace_limit (plans used for gradients)      */
 #define TN_N_GEMM_CONFIGS 8       /* tile configurations per precision              */
 
 typedef struct {
@@ -95,8 +98,18 @@ typedef struct {
                                  step uses the entry of its precision and nn with
                                  the nearest (nm, nk); copied at plan creation     */
   int32_t n_tune;
-  int32_t reserved[5];
+  int32_t checkpoint_policy;  /* tn_contract_backward: TN_CKPT_AUTO (every forward
+                                 value stored if the backward workspace fits
+                                 workspace_limit, else TN_CKPT_RECOMPUTE),
+                                 TN_CKPT_ALL, or TN_CKPT_RECOMPUTE (values used
+                                 inside one block of the schedule are recomputed
+                                 before that block's adjoint; the blocks are
+                                 chosen for the least recomputation within
+                                 workspace_limit)                                  */
+  int32_t reserved[4];
 } tn_plan_options;
+
+typedef enum { TN_CKPT_AUTO = 0, TN_CKPT_ALL = 1, TN_CKPT_RECOMPUTE = 2 } tn_checkpoint_policy;
 
 typedef struct {
   int32_t n_tensors, n_steps, n_index, n_sliced;
@@ -133,7 +146,10 @@ typedef struct {
   int64_t segment_table_offset;   /* their byte offset inside the workspace         */
   int32_t n_phase0;               /* schedule positions 0 .. n_phase0-1 run once
                                      (they depend on no outer sliced index)         */
+  int32_t backward_policy;        /* TN_CKPT_ALL or TN_CKPT_RECOMPUTE (in effect)   */
+  int32_t backward_blocks;        /* blocks of the backward schedule                */
   int32_t reserved_info;
+  double cmac_backward_recompute; /* multiply-adds the backward recomputes          */
 } tn_plan_info;
 
 /* One step as scheduled (tests, benchmarks, autotuning). */
@@ -246,17 +262,24 @@ tn_status tn_contract_noalloc(tn_plan_t plan, const void* const* leaves,
                               void* out, void* stream);
 
 /*
- * Adjoint of tn_contract with out_mode TN_OUT_SUM over all slices.
+ * Adjoint of tn_contract with out_mode TN_OUT_SUM over the slices
+ * slice_ids[n_slice_ids] (NULL, 0 = all; a slice listed twice counts twice):
+ * the sum over slices (Eq. sliced_sum) and every pairwise step are linear in
+ * each leaf, so the gradient is the reverse sweep of the steps, dA = dC.B^H
+ * and dB = A^H.dC, with the gradients of results shared by many slices
+ * summed over them, and with outer iterations accumulated.
  * grad_out: device complex128[out_elems], the gradient of a real loss with
  * respect to the output in PyTorch's convention (dL/d conj(out)).
  * grad_leaves[n_tensors]: device complex64 buffers shaped like the leaves;
  * the gradient of each leaf is ADDED to it (NULL entries are skipped).
- * ws / ws_bytes: at least info.workspace_backward_bytes.
- * Returns TN_E_UNSUPPORTED when the plan needs outer iterations.
+ * ws / ws_bytes: at least info.workspace_backward_bytes (the plan's
+ * checkpoint policy decides which forward values are stored and which are
+ * recomputed).  Returns TN_E_WORKSPACE for a smaller workspace and
+ * TN_E_INVALID for a slice id out of range.
  */
 tn_status tn_contract_backward(tn_plan_t plan, const void* const* leaves, const void* grad_out,
-                               void* const* grad_leaves, void* ws, size_t ws_bytes,
-                               void* stream);
+                               void* const* grad_leaves, const int64_t* slice_ids,
+                               int64_t n_slice_ids, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * tn_contract with timing of one step: ev_start / ev_stop (hipEvent_t created
@@ -308,6 +331,22 @@ typedef struct {
 tn_status tn_plan_segment_tables(tn_plan_t plan, const void* const* leaves, void* ws,
                                  void* blob, int64_t blob_bytes, tn_segment_layout* lay,
                                  int32_t max_lay, int32_t* n_lay);
+
+/*
+ * Backward schedule of the plan (tests and diagnostics; needs no GPU).  Per
+ * node (leaves 0..n_tensors-1, then one per step; 2*n_tensors-1 entries):
+ * keep (0: value recomputed inside its block, 1: stored from the forward
+ * pass, 2: not needed), frontier (1: a phase-0 result consumed by a phase-1
+ * step, whose gradient accumulates over outer iterations), and workspace byte
+ * offsets of the value in the forward pass, of the recomputed value and of
+ * the gradient (-1: none).  block_of[n_steps]: block of each schedule
+ * position (tn_plan_schedule order).  fuse_chain[info.n_chains] (may be
+ * NULL): 1 if the chain runs as one fused launch in the backward's forward
+ * pass.
+ */
+tn_status tn_plan_backward_tables(tn_plan_t plan, int8_t* keep, int8_t* frontier,
+                                  int64_t* value_off, int64_t* recompute_off, int64_t* grad_off,
+                                  int32_t* block_of, int8_t* fuse_chain);
 
 /* Chain ``i`` (0 <= i < info.n_chains) of the plan. */
 tn_status tn_plan_chain(tn_plan_t plan, int32_t i, tn_chain_info* out);

@@ -26,6 +26,9 @@ TN_FLAG_PERSISTENT = 16
 TN_FLAG_CHAIN_VALU = 32
 TN_FLAG_CHAIN_STEPWISE = 64
 TN_FLAG_CHAIN_NO_SINGLE = 128
+TN_FLAG_FIT_BACKWARD = 256
+TN_CKPT_AUTO, TN_CKPT_ALL, TN_CKPT_RECOMPUTE = 0, 1, 2
+_CKPT = {"auto": TN_CKPT_AUTO, "all": TN_CKPT_ALL, "recompute": TN_CKPT_RECOMPUTE}
 KIND_NAMES = {0: "simple", 1: "splitk", 2: "stream", 3: "gemm"}
 
 I8x48 = ctypes.c_int8 * 48
@@ -35,7 +38,8 @@ class PlanOptions(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_resident_bits", ctypes.c_int32),
                 ("workspace_limit", ctypes.c_int64), ("flags", ctypes.c_uint32),
                 ("gemm_config", ctypes.c_int32), ("tune", ctypes.POINTER(ctypes.c_int32)),
-                ("n_tune", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("n_tune", ctypes.c_int32), ("checkpoint_policy", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -52,7 +56,9 @@ class PlanInfo(ctypes.Structure):
                               "outer_slicebit")] + \
         [("n_chains", ctypes.c_int32), ("n_segments", ctypes.c_int32),
          ("segment_table_bytes", ctypes.c_int64), ("segment_table_offset", ctypes.c_int64),
-         ("n_phase0", ctypes.c_int32), ("reserved_info", ctypes.c_int32)]
+         ("n_phase0", ctypes.c_int32), ("backward_policy", ctypes.c_int32),
+         ("backward_blocks", ctypes.c_int32), ("reserved_info", ctypes.c_int32),
+         ("cmac_backward_recompute", ctypes.c_double)]
 
 
 class StepInfo(ctypes.Structure):
@@ -88,7 +94,7 @@ class SegmentLayout(ctypes.Structure):
 EXPORTS = ("tn_plan_create", "tn_plan_query", "tn_plan_step", "tn_contract",
            "tn_contract_probe", "tn_contract_backward", "tn_plan_destroy", "tn_last_error",
            "tn_permute", "tn_plan_chain", "tn_plan_schedule", "tn_plan_segment_tables",
-           "tn_contract_noalloc")
+           "tn_contract_noalloc", "tn_plan_backward_tables")
 NOALLOC_WORKSPACE_BYTES = 64 << 20
 
 _lib = None
@@ -118,11 +124,15 @@ def lib():
                                         ctypes.c_int64, ctypes.c_int32, P, P, ctypes.c_size_t, P,
                                         ctypes.c_int32, P, P]
         L.tn_contract_backward.restype = ctypes.c_int
-        L.tn_contract_backward.argtypes = [P, ctypes.POINTER(P), P, ctypes.POINTER(P), P,
+        L.tn_contract_backward.argtypes = [P, ctypes.POINTER(P), P, ctypes.POINTER(P),
+                                           ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, P,
                                            ctypes.c_size_t, P]
         L.tn_contract_noalloc.restype = ctypes.c_int
         L.tn_contract_noalloc.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_int64),
                                           ctypes.c_int64, ctypes.c_int32, P, P]
+        i8p, i64p = ctypes.POINTER(ctypes.c_int8), ctypes.POINTER(ctypes.c_int64)
+        L.tn_plan_backward_tables.restype = ctypes.c_int
+        L.tn_plan_backward_tables.argtypes = [P, i8p, i8p, i64p, i64p, i64p, i32p, i8p]
         L.tn_plan_schedule.restype = ctypes.c_int
         L.tn_plan_schedule.argtypes = [P, i32p, ctypes.c_int32]
         L.tn_plan_segment_tables.restype = ctypes.c_int
@@ -201,7 +211,8 @@ class Plan:
     def __init__(self, labels, dims, open_ids, path, sliced=(), precision="c64",
                  max_resident_bits=-1, workspace_limit="auto", no_reuse=False, simple=False,
                  gemm_config=-1, tune="default", persistent=False, chains=True,
-                 chain_mfma=True, chain_fused=True, chain_single=True):
+                 chain_mfma=True, chain_fused=True, chain_single=True, checkpoint="auto",
+                 fit_backward=False):
         n_index = (max(dims) + 1) if isinstance(dims, dict) else len(dims)
         dim_arr = [dims[i] for i in range(n_index)]
         ranks, r_p = _i32([len(l) for l in labels])
@@ -220,8 +231,10 @@ class Plan:
             (TN_FLAG_PERSISTENT if persistent else 0) | (0 if chains else TN_FLAG_NO_CHAIN) | \
             (0 if chain_mfma else TN_FLAG_CHAIN_VALU) | \
             (0 if chain_fused else TN_FLAG_CHAIN_STEPWISE) | \
-            (0 if chain_single else TN_FLAG_CHAIN_NO_SINGLE)
+            (0 if chain_single else TN_FLAG_CHAIN_NO_SINGLE) | \
+            (TN_FLAG_FIT_BACKWARD if fit_backward else 0)
         opts.gemm_config = gemm_config
+        opts.checkpoint_policy = _CKPT[checkpoint]
         entries = load_tune_table() if tune == "default" else (tune or [])
         tarr, t_p = _i32([x for e in entries for x in e] or [0])
         opts.tune = t_p
@@ -306,6 +319,26 @@ class Plan:
         arr = (ctypes.c_int32 * max(self.n_tensors - 1, 1))()
         _check(lib().tn_plan_schedule(self._h, arr, len(arr)))
         return list(arr)[:self.n_tensors - 1]
+
+    def backward_tables(self):
+        """Backward schedule (``tn_plan_backward_tables``) as numpy arrays."""
+        nodes = 2 * self.n_tensors - 1
+        nst = max(self.n_tensors - 1, 1)
+        nch = max(self.info()["n_chains"], 1)
+        keep = np.zeros(nodes, np.int8)
+        front = np.zeros(nodes, np.int8)
+        voff = np.zeros(nodes, np.int64)
+        roff = np.zeros(nodes, np.int64)
+        goff = np.zeros(nodes, np.int64)
+        blk = np.zeros(nst, np.int32)
+        fuse = np.zeros(nch, np.int8)
+        ptr = lambda a, t: a.ctypes.data_as(ctypes.POINTER(t))  # noqa: E731
+        _check(lib().tn_plan_backward_tables(
+            self._h, ptr(keep, ctypes.c_int8), ptr(front, ctypes.c_int8),
+            ptr(voff, ctypes.c_int64), ptr(roff, ctypes.c_int64), ptr(goff, ctypes.c_int64),
+            ptr(blk, ctypes.c_int32), ptr(fuse, ctypes.c_int8)))
+        return dict(keep=keep, frontier=front, value_off=voff, recompute_off=roff,
+                    grad_off=goff, block_of=blk[:self.n_tensors - 1], fuse_chain=fuse)
 
     def segment_tables(self, leaf_ptrs, ws_ptr):
         """Persistent-segment control tables for the given (integer) leaf and
@@ -399,8 +432,9 @@ class Plan:
                                          ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
         return out
 
-    def backward(self, leaves, grad_out, grad_leaves, stream=None):
-        """Adds d(loss)/d(leaf) (PyTorch convention) into ``grad_leaves``."""
+    def backward(self, leaves, grad_out, grad_leaves, slice_ids=None, stream=None):
+        """Adds d(loss)/d(leaf) (PyTorch convention) into ``grad_leaves`` for
+        the output summed over ``slice_ids`` (None = all slices)."""
         import torch
         inf = self.info()
         arr, dev = self._leaf_ptrs(leaves)
@@ -408,8 +442,14 @@ class Plan:
         g = grad_out.to(torch.complex128).contiguous()
         garr = (ctypes.c_void_p * self.n_tensors)(
             *[(x.data_ptr() if x is not None else None) for x in grad_leaves])
-        _check(lib().tn_contract_backward(self._h, arr, ctypes.c_void_p(g.data_ptr()), garr,
-                                          ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+        if slice_ids is not None:
+            sids = np.ascontiguousarray(np.asarray(slice_ids, dtype=np.int64))
+            sp = sids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+            nsel = len(sids)
+        else:
+            sids, sp, nsel = None, None, 0
+        _check(lib().tn_contract_backward(self._h, arr, ctypes.c_void_p(g.data_ptr()), garr, sp,
+                                          nsel, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                           _stream_ptr(stream)))
         return grad_leaves
 

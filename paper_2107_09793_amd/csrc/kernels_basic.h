@@ -372,23 +372,30 @@ __global__ void __launch_bounds__(kBlock) k_slice_sum(SumArgs p) {
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint of the slice sum: every resident slice of the root receives the
-// output gradient of its output element.
+// Adjoint of the slice sum: every resident slice of the root that the sum
+// took receives the output gradient of its output element (times the number
+// of times the slice was listed); n_sel < 0: every resident slice, once.
 struct RootGradArgs {
   const double2* grad_out;
   float2* dst;
   int32_t open_bits, res_bits, accumulate;
+  int32_t n_sel;
   int8_t s_open[kMaxBits], s_res[kMaxBits];
+  int32_t sel_r[kMaxSel];
+  float sel_w[kMaxSel];
 };
 
 __global__ void __launch_bounds__(kBlock) k_root_grad(RootGradArgs p) {
-  const uint64_t n = 1ull << (p.open_bits + p.res_bits);
+  const uint64_t rsel = p.n_sel < 0 ? 1ull << p.res_bits : (uint64_t)p.n_sel;
+  const uint64_t n = rsel << p.open_bits;
   for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
        i += (uint64_t)gridDim.x * kBlock) {
-    uint64_t o = i & ((1ull << p.open_bits) - 1), r = i >> p.open_bits;
+    const uint64_t o = i & ((1ull << p.open_bits) - 1), j = i >> p.open_bits;
+    const uint64_t r = p.n_sel < 0 ? j : (uint64_t)p.sel_r[j];
+    const float w = p.n_sel < 0 ? 1.f : p.sel_w[j];
     int64_t off = scatter(o, p.s_open, p.open_bits) + scatter(r, p.s_res, p.res_bits);
     double2 g = p.grad_out[o];
-    float2 v = make_float2((float)g.x, (float)g.y);
+    float2 v = make_float2(w * (float)g.x, w * (float)g.y);
     if (p.accumulate) {
       float2 c = p.dst[off];
       v.x += c.x;
@@ -396,6 +403,14 @@ __global__ void __launch_bounds__(kBlock) k_root_grad(RootGradArgs p) {
     }
     p.dst[off] = v;
   }
+}
+
+// complex64 zero fill (gradient buffers that accumulate; a kernel, not a
+// memset, so the call sequence can be captured in a graph).
+__global__ void __launch_bounds__(kBlock) k_fill_c64(float2* out, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock)
+    out[i] = make_float2(0.f, 0.f);
 }
 
 }  // namespace tnk

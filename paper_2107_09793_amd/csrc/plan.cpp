@@ -810,34 +810,204 @@ static void schedule_pass(Plan& p) {
     int32_t d = g.last - g.first;
     p.n_launches -= g.phase ? (int32_t)iters * d : d;
   }
+}
 
-  // backward: all forward results kept (checkpointing everything), gradient
-  // buffers of intermediates allocated when produced and freed after use.
-  p.bwd_fwd_off.assign(nn_nodes, -1);
-  p.bwd_grad_off.assign(nn_nodes, -1);
+// ---------------------------------------------------------------------------
+// Backward schedule (the adjoint of the contraction).  The sum over slices
+// (Eq. sliced_sum) and every pairwise step are linear in each operand, so the
+// adjoint runs the steps in reverse: for C = A.B, dA = dC.B^H and dB = A^H.dC
+// (conjugate-Wirtinger gradients), and a result shared by many slices (S_v
+// smaller than the full slice set) receives the sum of their gradients
+// through the folded instance bits of the adjoint product.  With outer
+// iterations, phase-1 steps run forward and backward once per iteration and
+// the gradients of phase-0 results consumed there accumulate across
+// iterations; phase 0 is then differentiated once.
+//
+// The simulated sequence of allocations below is exactly the sequence
+// tn_contract_backward executes:
+//   1. forward of phase 0 (fused chains where a block holds the whole chain);
+//   2. if there are outer iterations: zero the gradients of the phase-0
+//      results consumed by phase 1 ("frontier"), then per iteration: forward
+//      of phase 1, root gradient, adjoint of the phase-1 blocks in reverse;
+//      then the frontier values are dropped;
+//   3. (root gradient if phase 1 is empty,) adjoint of the phase-0 blocks.
+// The adjoint of a block first recomputes, step by step, the values the
+// block both produces and consumes (kept until their consumer's adjoint),
+// then walks the block's steps in reverse; a step's operand values and its
+// result's gradient are released right after its adjoint products.
+namespace {
+
+struct BwdEval {
+  int64_t peak = 0;
+  double recompute = 0;
+};
+
+BwdEval simulate_backward(const Plan& p, const std::vector<int32_t>& blk, bool fuse,
+                          BwdPlan* out) {
+  const int n = p.n_tensors, nsteps = n - 1, nodes = n + nsteps, root = nodes - 1;
+  const int N = (int)p.sched.size();
+  std::vector<int32_t> pos_of(nsteps, -1), cons(nodes, -1);
+  for (int q = 0; q < N; ++q) pos_of[p.sched[q]] = q;
+  for (int k = 0; k < nsteps; ++k) {
+    cons[p.steps[k].a] = k;
+    cons[p.steps[k].b] = k;
+  }
+  BwdPlan B;
+  B.block_of = blk;
+  B.keep.assign(nodes, 0);
+  B.frontier.assign(nodes, 0);
+  B.fwd_off.assign(nodes, -1);
+  B.rec_off.assign(nodes, -1);
+  B.grad_off.assign(nodes, -1);
+  B.fuse_chain.assign(p.chains.size(), 0);
+  const bool chains_on = fuse && !(p.flags & 64u);
+  for (size_t g = 0; g < p.chains.size(); ++g) {
+    bool one = chains_on;
+    for (int k = p.chains[g].first; k <= p.chains[g].last; ++k)
+      one &= blk[pos_of[k]] == blk[pos_of[p.chains[g].first]];
+    B.fuse_chain[g] = one;
+  }
+  const double iters = std::ldexp(1.0, p.outer_bits);
+  BwdEval ev;
+  for (int v = n; v < nodes; ++v) {
+    const int k = v - n;
+    if (v == root) {
+      B.keep[v] = 2;
+      continue;
+    }
+    const int kc = cons[v];
+    if (p.steps[k].phase != p.steps[kc].phase) {
+      B.keep[v] = 1;
+      B.frontier[v] = 1;
+    } else if (blk[pos_of[k]] != blk[pos_of[kc]]) {
+      B.keep[v] = 1;
+    } else {
+      B.keep[v] = 0;
+      ev.recompute += p.steps[k].cmac * (p.steps[k].phase ? iters : 1.0);
+    }
+  }
+  auto bytes = [&](int v) { return p.steps[v - n].c_bytes; };
+  Arena ar;
+  auto forward = [&](int q0, int q1) {
+    for (int q = q0; q < q1; ++q) {
+      const int k = p.sched[q];
+      const StepDesc& S = p.steps[k];
+      const bool fused = S.chain >= 0 && B.fuse_chain[S.chain];
+      if (fused && p.chains[S.chain].last != k) continue;
+      const int v = n + k;
+      B.fwd_off[v] = ar.alloc(bytes(v));
+      std::vector<int> ins;
+      if (fused) {
+        const ChainGroup& g = p.chains[S.chain];
+        ins.push_back(p.steps[g.first].a);
+        for (int j = g.first; j <= g.last; ++j) ins.push_back(p.steps[j].b);
+      } else {
+        ins = {S.a, S.b};
+      }
+      for (int x : ins)
+        if (x >= n && B.keep[x] == 0) ar.release(B.fwd_off[x], bytes(x));
+      if (B.keep[v] == 2) ar.release(B.fwd_off[v], bytes(v));
+    }
+  };
+  // blocks of a phase, as [begin, end) position ranges
+  auto blocks_of = [&](int q0, int q1) {
+    std::vector<std::pair<int, int>> r;
+    for (int q = q0; q < q1;) {
+      int e = q;
+      while (e < q1 && blk[e] == blk[q]) ++e;
+      r.push_back({q, e});
+      q = e;
+    }
+    return r;
+  };
+  auto adjoint = [&](int q0, int q1, int ph) {
+    auto bl = blocks_of(q0, q1);
+    for (int bi = (int)bl.size() - 1; bi >= 0; --bi) {
+      const int b0 = bl[bi].first, b1 = bl[bi].second;
+      for (int q = b0; q < b1; ++q) {
+        const int v = n + p.sched[q];
+        if (B.keep[v] == 0) B.rec_off[v] = ar.alloc(bytes(v));
+      }
+      for (int q = b1 - 1; q >= b0; --q) {
+        const StepDesc& S = p.steps[p.sched[q]];
+        for (int x : {S.a, S.b})
+          if (x >= n && B.grad_off[x] < 0) B.grad_off[x] = ar.alloc(bytes(x));
+        ar.release(B.grad_off[S.c], bytes(S.c));
+        for (int x : {S.a, S.b}) {
+          if (x < n) continue;
+          if (B.keep[x] == 0) ar.release(B.rec_off[x], bytes(x));
+          else if (!(B.frontier[x] && ph == 1)) ar.release(B.fwd_off[x], bytes(x));
+        }
+      }
+    }
+  };
+  const int n0 = p.n_phase0;
+  forward(0, n0);
+  if (n0 < N) {
+    for (int v = n; v < nodes; ++v)
+      if (B.frontier[v]) B.grad_off[v] = ar.alloc(bytes(v));
+    forward(n0, N);
+    B.grad_off[root] = ar.alloc(bytes(root));
+    adjoint(n0, N, 1);
+    for (int v = n; v < nodes; ++v)
+      if (B.frontier[v]) ar.release(B.fwd_off[v], bytes(v));
+  } else {
+    B.grad_off[root] = ar.alloc(bytes(root));
+  }
+  adjoint(0, n0, 0);
+  ev.peak = ar.top;
+  B.arena_bytes = ar.top;
+  B.cmac_recompute = ev.recompute;
+  B.block_begin.clear();
+  for (int q = 0; q < N; ++q)
+    if (q == 0 || blk[q] != blk[q - 1]) B.block_begin.push_back(q);
+  if (out) *out = std::move(B);
+  return ev;
+}
+
+// Blocks grown along each phase until their results hold at least T bytes,
+// never cutting inside a fused chain.
+std::vector<int32_t> blocks_by_bytes(const Plan& p, int64_t T, bool fuse) {
+  const int n = p.n_tensors, N = (int)p.sched.size();
+  std::vector<int32_t> pos_of(n - 1, -1);
+  for (int q = 0; q < N; ++q) pos_of[p.sched[q]] = q;
+  std::vector<uint8_t> no_cut_after(N, 0);
+  if (fuse && !(p.flags & 64u))
+    for (const ChainGroup& g : p.chains) {
+      int lo = N, hi = -1;
+      for (int k = g.first; k <= g.last; ++k) {
+        lo = std::min(lo, pos_of[k]);
+        hi = std::max(hi, pos_of[k]);
+      }
+      for (int q = lo; q < hi; ++q) no_cut_after[q] = 1;
+    }
+  std::vector<int32_t> blk(N, 0);
+  int id = 0;
+  int64_t acc = 0;
+  for (int q = 0; q < N; ++q) {
+    blk[q] = id;
+    acc += align_up(p.steps[p.sched[q]].c_bytes, 256);
+    const bool phase_end = q + 1 == p.n_phase0;
+    if (q + 1 < N && (phase_end || (acc >= T && !no_cut_after[q]))) {
+      ++id;
+      acc = 0;
+    }
+  }
+  return blk;
+}
+
+}  // namespace
+
+static void plan_backward(Plan& p, int64_t budget) {
+  const int n = p.n_tensors, nsteps = n - 1;
+  p.bwd = BwdPlan();
   if (nsteps == 0) {
-    p.bwd_arena_bytes = 0;
     p.workspace_bwd_bytes = 256;
     return;
   }
-  int64_t top = 0;
-  for (int k : p.sched) {
-    p.bwd_fwd_off[n + k] = top;
-    top += align_up(p.steps[k].c_bytes, 256);
-  }
-  Arena ga;
-  ga.top = top;
-  p.bwd_grad_off[root] = ga.alloc(p.steps[root - n].c_bytes);
-  for (int i = (int)p.sched.size() - 1; i >= 0; --i) {
-    const StepDesc& S = p.steps[p.sched[i]];
-    for (int x : {S.a, S.b})
-      if (x >= n) p.bwd_grad_off[x] = ga.alloc(p.steps[x - n].c_bytes);
-    ga.release(p.bwd_grad_off[S.c], S.c_bytes);
-  }
-  p.bwd_arena_bytes = ga.top;
-  // backward split-k scratch: the adjoint products have the same bit counts
-  // permuted among classes; reserve the forward maximum or the backward one
-  int64_t bscr = 0;
+  // split-k scratch: forward steps, and the adjoint products (same bit
+  // counts permuted among the classes)
+  int64_t bscr = p.scratch_bytes;
   for (const StepDesc& S : p.steps) {
     int nb = (int)S.bA.size(), nm = (int)S.mA.size(), nnb = (int)S.nB.size(), nk = (int)S.kA.size();
     int32_t ch;
@@ -847,7 +1017,41 @@ static void schedule_pass(Plan& p) {
     choose_kind(nb, nk, nnb, nm, p.flags, &ch, &sc);  // dB: rows k, cols n, sum m
     bscr = std::max(bscr, sc);
   }
-  p.workspace_bwd_bytes = align_up(p.bwd_arena_bytes, 256) + align_up(bscr, 256) + 256;
+  const int N = (int)p.sched.size();
+  std::vector<int32_t> all(N);
+  std::iota(all.begin(), all.end(), 0);
+  BwdEval e_all = simulate_backward(p, all, false, nullptr);
+  auto total = [&](int64_t arena) { return align_up(arena, 256) + align_up(bscr, 256) + 256; };
+  const bool all_fits = budget <= 0 || total(e_all.peak) <= budget;
+  if (p.ckpt_policy == CKPT_ALL || (p.ckpt_policy == CKPT_AUTO && all_fits)) {
+    simulate_backward(p, all, false, &p.bwd);
+    p.bwd.policy = CKPT_ALL;
+  } else {
+    // thresholds on the bytes a block produces, doubling; keep the one with
+    // the least recomputation that fits the budget (else the smallest peak)
+    int64_t lo = 256, hi = 0;
+    for (const StepDesc& S : p.steps) hi += align_up(S.c_bytes, 256);
+    std::vector<int32_t> best_blk;
+    BwdEval best;
+    bool best_fits = false;
+    for (double Tf = (double)lo; Tf <= 2.0 * (double)hi; Tf *= 1.41421356) {
+      const int64_t T = (int64_t)Tf;
+      std::vector<int32_t> blk = blocks_by_bytes(p, T, true);
+      BwdEval e = simulate_backward(p, blk, true, nullptr);
+      const bool fits = budget <= 0 || total(e.peak) <= budget;
+      if (best_blk.empty() || (fits && !best_fits) ||
+          (fits && best_fits && e.recompute < best.recompute) ||
+          (!fits && !best_fits && e.peak < best.peak)) {
+        best_blk = blk;
+        best = e;
+        best_fits = fits;
+      }
+    }
+    simulate_backward(p, best_blk, true, &p.bwd);
+    p.bwd.policy = CKPT_RECOMPUTE;
+  }
+  p.bwd.scratch_bytes = bscr;
+  p.workspace_bwd_bytes = total(p.bwd.arena_bytes);
 }
 
 std::string build_plan(Plan& p, int32_t n_tensors, const int32_t* ranks,
@@ -856,8 +1060,10 @@ std::string build_plan(Plan& p, int32_t n_tensors, const int32_t* ranks,
                        const int32_t* path, int32_t n_sliced, const int32_t* sliced_ids,
                        int32_t precision, int32_t max_resident_bits, int64_t ws_limit,
                        uint32_t flags, int32_t gemm_config, const int32_t* tune, int32_t n_tune,
-                       bool* unsupported) {
+                       int32_t ckpt_policy, bool* unsupported) {
   *unsupported = false;
+  if (ckpt_policy < CKPT_AUTO || ckpt_policy > CKPT_RECOMPUTE) return "unknown checkpoint policy";
+  p.ckpt_policy = ckpt_policy;
   if (gemm_config >= kNumGemmConfigs) return "gemm_config out of range";
   if (n_tune < 0 || (n_tune > 0 && !tune)) return "bad tune table";
   p.gemm_config = gemm_config < 0 ? -1 : gemm_config;
@@ -1030,10 +1236,16 @@ std::string build_plan(Plan& p, int32_t n_tensors, const int32_t* ranks,
     p.outer_idx = p.sliced_ids;
   }
   schedule(p);
-  auto too_big = [&](const Plan& q) {
+  // TN_FLAG_FIT_BACKWARD: the backward's workspace must fit the limit too
+  const bool fit_bwd = (flags & 256u) && ws_limit > 0;
+  auto too_big = [&](Plan& q) {
     if (max_resident_bits >= 0 && q.resident_bits > max_resident_bits) return true;
     if (ws_limit > 0 && q.arena_bytes > ws_limit) return true;
     if (q.max_log2_res > kMaxTensorBits) return true;
+    if (fit_bwd) {
+      plan_backward(q, ws_limit);
+      if (q.workspace_bwd_bytes > ws_limit) return true;
+    }
     return false;
   };
   while (too_big(p)) {
@@ -1081,6 +1293,7 @@ std::string build_plan(Plan& p, int32_t n_tensors, const int32_t* ranks,
       return "a step has more than 48 bits in one class";
     }
   }
+  plan_backward(p, ws_limit);
   return "";
 }
 

@@ -103,6 +103,30 @@ struct ChainGroup {
   std::vector<ChainStepDesc> st;
 };
 
+// Backward (adjoint) schedule.  The forward values a step's adjoint needs
+// are either stored from the forward pass or recomputed: the schedule is cut
+// into blocks; a value consumed in the block that produced it is freed in the
+// forward pass and recomputed (and then kept) just before that block's
+// adjoint runs, while a value crossing a block boundary (or the phase
+// boundary) is stored from the forward pass until its consumer's adjoint.
+// Every position its own block stores everything (no recomputation).
+enum CheckpointPolicy : int32_t { CKPT_AUTO = 0, CKPT_ALL = 1, CKPT_RECOMPUTE = 2 };
+
+struct BwdPlan {
+  int32_t policy = CKPT_ALL;         // the policy in effect (ALL or RECOMPUTE)
+  std::vector<int32_t> block_of;     // block id of each schedule position
+  std::vector<int32_t> block_begin;  // first position of each block (ascending)
+  std::vector<uint8_t> keep;         // per node: 0 recomputed, 1 stored, 2 not needed (root)
+  std::vector<uint8_t> frontier;     // per node: phase-0 result consumed by a phase-1 step
+  std::vector<uint8_t> fuse_chain;   // per chain: fused launch in the backward's forward pass
+  std::vector<int64_t> fwd_off;      // per node: value offset in the forward pass (-1 none)
+  std::vector<int64_t> rec_off;      // per node: value offset when recomputed (-1 none)
+  std::vector<int64_t> grad_off;     // per node: gradient offset (-1 none)
+  int64_t arena_bytes = 0;
+  int64_t scratch_bytes = 0;         // split-k partials of forward and adjoint products
+  double cmac_recompute = 0;         // multiply-adds recomputed (all outer iterations)
+};
+
 struct LeafDesc {
   std::vector<int32_t> bits;      // global bit ids (all), layout order lsb first
   std::vector<int8_t> log2s;      // stride of each bit
@@ -156,9 +180,8 @@ struct Plan {
   // memory
   int64_t arena_bytes = 0, bytes_no_deletion = 0, scratch_bytes = 0;
   int64_t ctrl_bytes = 0, workspace_bytes = 0, workspace_bwd_bytes = 0;
-  int64_t bwd_arena_bytes = 0;
-  std::vector<int64_t> bwd_fwd_off;   // backward: forward result offsets (nothing freed)
-  std::vector<int64_t> bwd_grad_off;  // backward: gradient buffer offsets per node
+  int32_t ckpt_policy = CKPT_AUTO;    // requested
+  BwdPlan bwd;
 
   // statistics
   double cmac_reuse = 0, cmac_noreuse = 0, cmac_exec = 0, cmac_sl = 0, f_sl = 0;
@@ -184,6 +207,6 @@ std::string build_plan(Plan& p, int32_t n_tensors, const int32_t* ranks,
                        const int32_t* path, int32_t n_sliced, const int32_t* sliced_ids,
                        int32_t precision, int32_t max_resident_bits, int64_t ws_limit,
                        uint32_t flags, int32_t gemm_config, const int32_t* tune, int32_t n_tune,
-                       bool* unsupported);
+                       int32_t ckpt_policy, bool* unsupported);
 
 }  // namespace tn

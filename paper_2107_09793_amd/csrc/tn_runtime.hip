@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <new>
@@ -263,18 +264,23 @@ struct Ctx {
   hipStream_t st;
 };
 
+// Element offset of leaf t's sub-block for outer iteration outer_val (its
+// outer sliced bits fixed to that iteration's values).
+int64_t leaf_outer_off(const tn::Plan& p, int t, uint64_t outer_val) {
+  const tn::LeafDesc& L = p.leaves[t];
+  int64_t off = 0;
+  for (size_t i = 0; i < L.outer_bits.size(); ++i) {
+    int bit = L.outer_bits[i];
+    for (int j = 0; j < p.outer_bits; ++j)
+      if (p.outer_bit_ids[j] == bit && ((outer_val >> j) & 1)) off += (int64_t)1 << L.outer_log2s[i];
+  }
+  return off;
+}
+
 const float2* node_ptr(const Ctx& c, int node, uint64_t outer_val) {
   const tn::Plan& p = c.p;
-  if (node < p.n_tensors) {
-    const tn::LeafDesc& L = p.leaves[node];
-    int64_t off = 0;
-    for (size_t i = 0; i < L.outer_bits.size(); ++i) {
-      int bit = L.outer_bits[i];
-      for (int j = 0; j < p.outer_bits; ++j)
-        if (p.outer_bit_ids[j] == bit && ((outer_val >> j) & 1)) off += (int64_t)1 << L.outer_log2s[i];
-    }
-    return static_cast<const float2*>(c.leaves[node]) + off;
-  }
+  if (node < p.n_tensors)
+    return static_cast<const float2*>(c.leaves[node]) + leaf_outer_off(p, node, outer_val);
   return reinterpret_cast<const float2*>(c.ws + p.steps[node - p.n_tensors].c_off);
 }
 
@@ -302,8 +308,21 @@ tn_status run_step(const Ctx& c, int k, uint64_t outer_val, Probe* probe = nullp
 }
 
 // One fused chain (all its steps, one launch).
+// Operand addresses of a launch: node id -> device pointer.
+using NodeSrc = std::function<const float2*(int)>;
+
+tn_status run_chain_with(const Ctx& c, const tn::ChainGroup& g, const NodeSrc& src, float2* Y,
+                         Probe* probe);
+
 tn_status run_chain(const Ctx& c, const tn::ChainGroup& g, uint64_t outer_val,
                     Probe* probe = nullptr) {
+  return run_chain_with(
+      c, g, [&](int x) { return node_ptr(c, x, outer_val); },
+      reinterpret_cast<float2*>(c.ws + c.p.steps[g.last].c_off), probe);
+}
+
+tn_status run_chain_with(const Ctx& c, const tn::ChainGroup& g, const NodeSrc& src, float2* Y,
+                         Probe* probe) {
   const tn::Plan& p = c.p;
   static_assert(sizeof(tnk::ChainArgs) % 4 == 0, "argument copy in 32-bit words");
   static_assert(tnk::kChainSteps == tn::kChainMaxSteps && tnk::kChainTile == tn::kChainTileBits &&
@@ -313,9 +332,8 @@ tn_status run_chain(const Ctx& c, const tn::ChainGroup& g, uint64_t outer_val,
   tnk::ChainArgs a;
   memset(&a, 0, sizeof a);
   const tn::StepDesc& F = p.steps[g.first];
-  const tn::StepDesc& L = p.steps[g.last];
-  a.X = node_ptr(c, F.a, outer_val);
-  a.Y = reinterpret_cast<float2*>(c.ws + L.c_off);
+  a.X = src(F.a);
+  a.Y = Y;
   a.nsteps = (int32_t)g.st.size();
   a.tin = (int32_t)g.in_slot.size();
   a.tout = (int32_t)g.out_slot.size();
@@ -339,7 +357,7 @@ tn_status run_chain(const Ctx& c, const tn::ChainGroup& g, uint64_t outer_val,
     if (d.kslot.size() > 6 || d.nslot.size() > 6 || d.rslot.size() > (size_t)tnk::kChainTile ||
         d.bB.size() > (size_t)tnk::kChainTile)
       return fail(TN_E_INVALID, "chain step exceeds its descriptor");
-    t.B = node_ptr(c, p.steps[d.step].b, outer_val);
+    t.B = src(p.steps[d.step].b);
     t.nk = (int8_t)d.kslot.size();
     t.nn = (int8_t)d.nslot.size();
     t.nrow = (int8_t)d.nrow;
@@ -547,7 +565,8 @@ tn_status tn_plan_create(int32_t n_tensors, const int32_t* ranks, const int32_t*
     std::string err = tn::build_plan(h->p, n_tensors, ranks, index_ids, n_index, index_dims,
                                      n_open, open_ids, n_steps, path, n_sliced, sliced_ids,
                                      o.precision, o.max_resident_bits, o.workspace_limit,
-                                     o.flags, o.gemm_config, o.tune, o.n_tune, &unsup);
+                                     o.flags, o.gemm_config, o.tune, o.n_tune,
+                                     o.checkpoint_policy, &unsup);
     if (!err.empty()) {
       delete h;
       return fail(unsup ? TN_E_UNSUPPORTED : TN_E_INVALID, err);
@@ -598,6 +617,9 @@ tn_status tn_plan_query(tn_plan_t plan, tn_plan_info* out) {
   out->segment_table_bytes = p.persist_bytes;
   out->segment_table_offset = al256(p.arena_bytes) + al256(p.scratch_bytes) + p.ctrl_bytes;
   out->n_phase0 = p.n_phase0;
+  out->backward_policy = p.bwd.policy;
+  out->backward_blocks = (int32_t)p.bwd.block_begin.size();
+  out->cmac_backward_recompute = p.bwd.cmac_recompute;
   return TN_OK;
 }
 
@@ -710,6 +732,27 @@ tn_status tn_plan_segment_tables(tn_plan_t plan, const void* const* leaves, void
   } catch (const std::bad_alloc&) {
     return fail(TN_E_OOM, "host allocation failed");
   }
+}
+
+tn_status tn_plan_backward_tables(tn_plan_t plan, int8_t* keep, int8_t* frontier,
+                                  int64_t* value_off, int64_t* recompute_off, int64_t* grad_off,
+                                  int32_t* block_of, int8_t* fuse_chain) {
+  if (!plan || !keep || !frontier || !value_off || !recompute_off || !grad_off || !block_of)
+    return fail(TN_E_INVALID, "NULL argument");
+  const tn::BwdPlan& B = plan->p.bwd;
+  const size_t nodes = (size_t)(2 * plan->p.n_tensors - 1);
+  for (size_t v = 0; v < nodes; ++v) {
+    const bool has = v < B.keep.size();
+    keep[v] = has ? (int8_t)B.keep[v] : 0;
+    frontier[v] = has ? (int8_t)B.frontier[v] : 0;
+    value_off[v] = has ? B.fwd_off[v] : -1;
+    recompute_off[v] = has ? B.rec_off[v] : -1;
+    grad_off[v] = has ? B.grad_off[v] : -1;
+  }
+  for (size_t q = 0; q < B.block_of.size(); ++q) block_of[q] = B.block_of[q];
+  if (fuse_chain)
+    for (size_t g = 0; g < B.fuse_chain.size(); ++g) fuse_chain[g] = (int8_t)B.fuse_chain[g];
+  return TN_OK;
 }
 
 tn_status tn_plan_schedule(tn_plan_t plan, int32_t* order, int32_t n) {
@@ -945,63 +988,139 @@ tn_status tn_contract_noalloc(tn_plan_t plan, const void* const* leaves, const i
 extern "C" {
 
 tn_status tn_contract_backward(tn_plan_t plan, const void* const* leaves, const void* grad_out,
-                               void* const* grad_leaves, void* ws, size_t ws_bytes,
-                               void* stream) {
+                               void* const* grad_leaves, const int64_t* slice_ids,
+                               int64_t n_slice_ids, void* ws, size_t ws_bytes, void* stream) {
   if (!plan || !leaves || !grad_out || !grad_leaves) return fail(TN_E_INVALID, "NULL argument");
   const tn::Plan& p = plan->p;
-  if (p.outer_bits > 0)
-    return fail(TN_E_UNSUPPORTED, "backward needs every slice resident (no outer iterations)");
+  const tn::BwdPlan& B = p.bwd;
   if ((int64_t)ws_bytes < p.workspace_bwd_bytes || !ws)
     return fail(TN_E_WORKSPACE, "workspace smaller than tn_plan_info.workspace_backward_bytes");
+  if (n_slice_ids < 0 || (n_slice_ids > 0 && !slice_ids))
+    return fail(TN_E_INVALID, "bad slice list");
   for (int t = 0; t < p.n_tensors; ++t)
     if (!leaves[t]) return fail(TN_E_INVALID, "NULL leaf pointer");
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* W = static_cast<char*>(ws);
-  float2* scratch = reinterpret_cast<float2*>(W + ((p.bwd_arena_bytes + 255) / 256) * 256);
   const int n = p.n_tensors;
-  auto fwd_ptr = [&](int node) -> float2* {
-    if (node < n) return const_cast<float2*>(static_cast<const float2*>(leaves[node]));
-    return reinterpret_cast<float2*>(W + p.bwd_fwd_off[node]);
-  };
-  // forward, keeping every intermediate
-  for (int k : p.sched) {
-    const tn::StepDesc& S = p.steps[k];
-    tnk::StepArgs a = make_args(S);
-    a.A = fwd_ptr(S.a);
-    a.B = fwd_ptr(S.b);
-    a.C = fwd_ptr(S.c);
-    tn_status s = launch_step(S.kind, S.splitk_chunks, S.tile, a, scratch, p.precision, st);
-    if (s != TN_OK) return s;
+  // selected resident slices per outer iteration, with multiplicity
+  const bool all = n_slice_ids == 0;
+  std::map<uint64_t, std::map<int32_t, int32_t>> sel;
+  for (int64_t i = 0; i < n_slice_ids; ++i) {
+    const int64_t s = slice_ids[i];
+    if (s < 0 || s >= p.n_slices) return fail(TN_E_INVALID, "slice id out of range");
+    uint64_t it = 0, r = 0;
+    for (int j = 0; j < p.outer_bits; ++j) it |= (uint64_t)((s >> p.outer_slicebit[j]) & 1) << j;
+    for (int j = 0; j < p.resident_bits; ++j) r |= (uint64_t)((s >> p.res_slicebit[j]) & 1) << j;
+    sel[it][(int32_t)r]++;
   }
-  // gradient of the root: the output gradient, broadcast over resident slices
-  const int root = n + (n - 1) - 1;
-  tnk::RootGradArgs rg;
-  memset(&rg, 0, sizeof rg);
-  rg.grad_out = static_cast<const double2*>(grad_out);
-  rg.open_bits = p.open_bits;
-  rg.res_bits = p.resident_bits;
-  copy_bits(rg.s_open, p.root_open_log2);
-  copy_bits(rg.s_res, p.root_res_log2);
-  if (n == 1) {
+  if (n == 1) {   // the output is the leaf itself
     if (!grad_leaves[0]) return TN_OK;
+    tnk::RootGradArgs rg;
+    memset(&rg, 0, sizeof rg);
+    rg.grad_out = static_cast<const double2*>(grad_out);
     rg.dst = static_cast<float2*>(grad_leaves[0]);
+    rg.open_bits = p.open_bits;
     rg.accumulate = 1;
-  } else {
-    rg.dst = reinterpret_cast<float2*>(W + p.bwd_grad_off[root]);
+    rg.n_sel = -1;
+    copy_bits(rg.s_open, p.root_open_log2);
+    hipLaunchKernelGGL(tnk::k_root_grad, dim3(grid_for(1ull << p.open_bits)), dim3(tnk::kBlock),
+                       0, st, rg);
+    TN_HIP_CHECK(hipGetLastError());
+    return TN_OK;
   }
-  hipLaunchKernelGGL(tnk::k_root_grad, dim3(grid_for(1ull << (p.open_bits + p.resident_bits))),
-                     dim3(tnk::kBlock), 0, st, rg);
-  TN_HIP_CHECK(hipGetLastError());
-  // reverse sweep: dA = dC . B^H, dB = A^H . dC
-  for (int i = (int)p.sched.size() - 1; i >= 0; --i) {
-    const tn::StepDesc& S = p.steps[p.sched[i]];
-    float2* gC = reinterpret_cast<float2*>(W + p.bwd_grad_off[S.c]);
+  float2* scratch = reinterpret_cast<float2*>(W + al256(B.arena_bytes));
+  Ctx c{p, leaves, W, scratch, st};
+  const int root = n + (n - 1) - 1;
+  auto at = [&](int64_t off) { return reinterpret_cast<float2*>(W + off); };
+  // value of node x: a leaf (offset for the outer iteration), or the stored /
+  // recomputed result (rec: inside a block's adjoint, where values the block
+  // both produces and consumes live at their recomputed offsets)
+  auto val = [&](int x, uint64_t it, bool rec) -> float2* {
+    if (x < n)
+      return const_cast<float2*>(static_cast<const float2*>(leaves[x])) + leaf_outer_off(p, x, it);
+    return at(rec && B.keep[x] == 0 ? B.rec_off[x] : B.fwd_off[x]);
+  };
+  auto grad = [&](int x, uint64_t it) -> float2* {
+    if (x < n)
+      return grad_leaves[x] ? static_cast<float2*>(grad_leaves[x]) + leaf_outer_off(p, x, it)
+                            : nullptr;
+    return at(B.grad_off[x]);
+  };
+  auto launch_fwd = [&](const tn::StepDesc& S, float2* A, float2* Bp, float2* C) {
+    tnk::StepArgs a = make_args(S);
+    a.A = A;
+    a.B = Bp;
+    a.C = C;
+    return launch_step(S.kind, S.splitk_chunks, S.tile, a, scratch, p.precision, st);
+  };
+  auto forward = [&](int q0, int q1, uint64_t it) -> tn_status {
+    for (int q = q0; q < q1; ++q) {
+      const int k = p.sched[q];
+      const tn::StepDesc& S = p.steps[k];
+      const bool fused = S.chain >= 0 && B.fuse_chain[S.chain];
+      if (!fused && n + k == root) continue;   // the output value itself is not needed
+      if (fused) {
+        const tn::ChainGroup& g = p.chains[S.chain];
+        if (g.last != k) continue;
+        tn_status s = run_chain_with(
+            c, g, [&](int x) -> const float2* { return val(x, it, false); },
+            at(B.fwd_off[n + k]), nullptr);
+        if (s != TN_OK) return s;
+        continue;
+      }
+      tn_status s = launch_fwd(S, val(S.a, it, false), val(S.b, it, false), at(B.fwd_off[n + k]));
+      if (s != TN_OK) return s;
+    }
+    return TN_OK;
+  };
+  auto fill0 = [&](float2* dst, int64_t elems) -> tn_status {
+    hipLaunchKernelGGL(tnk::k_fill_c64, dim3(grid_for((uint64_t)elems, 1u << 20)),
+                       dim3(tnk::kBlock), 0, st, dst, elems);
+    TN_HIP_CHECK(hipGetLastError());
+    return TN_OK;
+  };
+  // gradient of the root for one outer iteration: the output gradient at
+  // every selected resident slice (times its multiplicity), zero elsewhere
+  auto root_grad = [&](uint64_t it) -> tn_status {
+    tnk::RootGradArgs rg;
+    memset(&rg, 0, sizeof rg);
+    rg.grad_out = static_cast<const double2*>(grad_out);
+    rg.dst = at(B.grad_off[root]);
+    rg.open_bits = p.open_bits;
+    rg.res_bits = p.resident_bits;
+    copy_bits(rg.s_open, p.root_open_log2);
+    copy_bits(rg.s_res, p.root_res_log2);
+    const uint64_t n_all = 1ull << (p.open_bits + p.resident_bits);
+    if (all) {
+      rg.n_sel = -1;
+      hipLaunchKernelGGL(tnk::k_root_grad, dim3(grid_for(n_all)), dim3(tnk::kBlock), 0, st, rg);
+      TN_HIP_CHECK(hipGetLastError());
+      return TN_OK;
+    }
+    tn_status s = fill0(rg.dst, (int64_t)n_all);
+    if (s != TN_OK) return s;
+    std::vector<std::pair<int32_t, int32_t>> v(sel[it].begin(), sel[it].end());
+    for (size_t i0 = 0; i0 < v.size(); i0 += tnk::kMaxSel) {
+      const size_t cnt = std::min(v.size() - i0, (size_t)tnk::kMaxSel);
+      rg.n_sel = (int32_t)cnt;
+      for (size_t i = 0; i < cnt; ++i) {
+        rg.sel_r[i] = v[i0 + i].first;
+        rg.sel_w[i] = (float)v[i0 + i].second;
+      }
+      hipLaunchKernelGGL(tnk::k_root_grad, dim3(grid_for((uint64_t)cnt << p.open_bits)),
+                         dim3(tnk::kBlock), 0, st, rg);
+      TN_HIP_CHECK(hipGetLastError());
+    }
+    return TN_OK;
+  };
+  // adjoint products of one step: dA (+)= dC . B^H, dB (+)= A^H . dC
+  auto adjoint_step = [&](const tn::StepDesc& S, uint64_t it) -> tn_status {
+    float2* gC = grad(S.c, it);
     const int nb = (int)S.bA.size(), nm = (int)S.mA.size(), nn = (int)S.nB.size(),
               nk = (int)S.kA.size();
-    float2* dA = S.a < n ? static_cast<float2*>(grad_leaves[S.a])
-                         : reinterpret_cast<float2*>(W + p.bwd_grad_off[S.a]);
-    float2* dB = S.b < n ? static_cast<float2*>(grad_leaves[S.b])
-                         : reinterpret_cast<float2*>(W + p.bwd_grad_off[S.b]);
+    float2* dA = grad(S.a, it);
+    float2* dB = grad(S.b, it);
+    auto acc = [&](int x) { return x < n || B.frontier[x] ? 1 : 0; };
     if (dA) {
       tnk::StepArgs a;
       memset(&a, 0, sizeof a);
@@ -1010,10 +1129,10 @@ tn_status tn_contract_backward(tn_plan_t plan, const void* const* leaves, const 
       copy_bits(a.sB_b, S.bB); copy_bits(a.sB_k, S.nB); copy_bits(a.sB_n, S.kB);
       copy_bits(a.sC_b, S.bA); copy_bits(a.sC_m, S.mA); copy_bits(a.sC_n, S.kA);
       a.A = gC;
-      a.B = fwd_ptr(S.b);
+      a.B = val(S.b, it, true);
       a.C = dA;
       a.conjB = 1;
-      a.accumulate = S.a < n ? 1 : 0;
+      a.accumulate = acc(S.a);
       int32_t ch;
       int64_t scr;
       int32_t kind = tn::choose_kind(a.nb, a.nm, a.nn, a.nk, p.flags, &ch, &scr);
@@ -1028,11 +1147,11 @@ tn_status tn_contract_backward(tn_plan_t plan, const void* const* leaves, const 
       copy_bits(a.sA_b, S.bA); copy_bits(a.sA_m, S.kA); copy_bits(a.sA_k, S.mA);
       copy_bits(a.sB_b, S.bC); copy_bits(a.sB_k, S.mC); copy_bits(a.sB_n, S.nC);
       copy_bits(a.sC_b, S.bB); copy_bits(a.sC_m, S.kB); copy_bits(a.sC_n, S.nB);
-      a.A = fwd_ptr(S.a);
+      a.A = val(S.a, it, true);
       a.B = gC;
       a.C = dB;
       a.conjA = 1;
-      a.accumulate = S.b < n ? 1 : 0;
+      a.accumulate = acc(S.b);
       int32_t ch;
       int64_t scr;
       int32_t kind = tn::choose_kind(a.nb, a.nm, a.nn, a.nk, p.flags, &ch, &scr);
@@ -1040,8 +1159,56 @@ tn_status tn_contract_backward(tn_plan_t plan, const void* const* leaves, const 
       tn_status s = launch_step(kind, ch, tile, a, scratch, p.precision, st);
       if (s != TN_OK) return s;
     }
+    return TN_OK;
+  };
+  // adjoint of the blocks of [q0, q1), last block first
+  auto adjoint = [&](int q0, int q1, uint64_t it) -> tn_status {
+    std::vector<std::pair<int, int>> bl;
+    for (int q = q0; q < q1;) {
+      int e = q;
+      while (e < q1 && B.block_of[e] == B.block_of[q]) ++e;
+      bl.push_back({q, e});
+      q = e;
+    }
+    for (int bi = (int)bl.size() - 1; bi >= 0; --bi) {
+      const int b0 = bl[bi].first, b1 = bl[bi].second;
+      for (int q = b0; q < b1; ++q) {   // recompute what the block produces and consumes
+        const tn::StepDesc& S = p.steps[p.sched[q]];
+        if (B.keep[S.c] != 0) continue;
+        tn_status s = launch_fwd(S, val(S.a, it, true), val(S.b, it, true), at(B.rec_off[S.c]));
+        if (s != TN_OK) return s;
+      }
+      for (int q = b1 - 1; q >= b0; --q) {
+        tn_status s = adjoint_step(p.steps[p.sched[q]], it);
+        if (s != TN_OK) return s;
+      }
+    }
+    return TN_OK;
+  };
+  const int n0 = p.n_phase0, N = (int)p.sched.size();
+  tn_status s = forward(0, n0, 0);
+  if (s != TN_OK) return s;
+  if (n0 < N) {
+    for (int v = n; v <= root; ++v)
+      if (B.frontier[v]) {
+        s = fill0(at(B.grad_off[v]), p.steps[v - n].c_bytes / 8);
+        if (s != TN_OK) return s;
+      }
+    const uint64_t n_it = 1ull << p.outer_bits;
+    for (uint64_t it = 0; it < n_it; ++it) {
+      if (!all && sel.find(it) == sel.end()) continue;
+      if ((s = forward(n0, N, it)) != TN_OK) return s;
+      if ((s = root_grad(it)) != TN_OK) return s;
+      if ((s = adjoint(n0, N, it)) != TN_OK) return s;
+    }
+  } else {
+    if (!all && sel.find(0) == sel.end()) {
+      // nothing selected: every gradient is zero (leaf gradients unchanged)
+      return TN_OK;
+    }
+    if ((s = root_grad(0)) != TN_OK) return s;
   }
-  return TN_OK;
+  return adjoint(0, n0, 0);
 }
 
 tn_status tn_permute(const void* in, void* out, int32_t nbits, const int8_t* in_log2,

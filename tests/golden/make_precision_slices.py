@@ -8,6 +8,9 @@ slicer), which bounds host memory; the sum of sub-slices is exactly the slice
 (Eq. sliced_sum).
 
     python tests/golden/make_precision_slices.py [slice ids ...]
+
+Default: 16 slices, ids 0, 1, 513, 1023 and 12 more drawn with
+numpy.random.default_rng([0, 5]) from the rest.
 """
 
 import hashlib
@@ -32,8 +35,15 @@ def fingerprint(w):
     return h.hexdigest()[:16]
 
 
+def default_ids():
+    fixed = [0, 1, 513, 1023]
+    rest = np.setdiff1d(np.arange(1024), fixed)
+    more = np.random.default_rng([0, 5]).choice(rest, size=12, replace=False)
+    return fixed + sorted(int(x) for x in more)
+
+
 def main():
-    ids = [int(x) for x in sys.argv[1:]] or [0, 1, 513, 1023]
+    ids = [int(x) for x in sys.argv[1:]] or default_ids()
     w = workloads.build("precision", seed=0)
     ts = slicing.TreeSets(w.tn.labels, w.tn.dims, w.tn.open, w.path)
     ext = slicing.greedy_slices(ts, n_slice=len(w.sliced) + 2)

@@ -1,4 +1,4 @@
-"""The plan tests and the persistent-segment table tests, run against a
+"""The plan, backward-schedule and persistent-segment table tests, run against a
 build of the library whose host code carries AddressSanitizer and
 UndefinedBehaviorSanitizer (plan construction, descriptor and chain tables,
 the C ABI's argument checks).  Any report aborts the child run."""
@@ -21,7 +21,8 @@ def test_plan_tests_clean_under_host_sanitizers():
                ASAN_OPTIONS="detect_leaks=0:halt_on_error=1:abort_on_error=1",
                UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        "tests/test_plan.py", "tests/test_persist_tables.py"],
+                        "tests/test_plan.py", "tests/test_persist_tables.py",
+                        "tests/test_backward_plan.py"],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=1200)
     tail = (r.stdout + r.stderr)[-4000:]
     assert r.returncode == 0, tail

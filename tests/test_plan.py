@@ -335,7 +335,7 @@ def test_workspace_too_small_is_reported():
         assert st == binding.TN_E_WORKSPACE
         assert b"workspace" in L.tn_last_error()
     grads = (ctypes.c_void_p * pl.n_tensors)(*([0x4000] * pl.n_tensors))
-    st = L.tn_contract_backward(pl._h, fake, ctypes.c_void_p(0x2000), grads,
+    st = L.tn_contract_backward(pl._h, fake, ctypes.c_void_p(0x2000), grads, None, 0,
                                 ctypes.c_void_p(0x3000), info["workspace_backward_bytes"] - 1,
                                 None)
     assert st == binding.TN_E_WORKSPACE
