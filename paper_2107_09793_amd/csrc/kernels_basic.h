@@ -333,39 +333,42 @@ struct SumArgs {
 
 __global__ void __launch_bounds__(kBlock) k_slice_sum(SumArgs p) {
   const uint64_t n_out = 1ull << p.open_bits;
-  uint64_t o = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (o >= n_out) return;
-  int64_t oo = scatter(o, p.s_open, p.open_bits);
-  if (p.mode == 0) {
-    double2 acc = p.out[o];
-    if (p.n_sel < 0) {
-      uint64_t R = 1ull << p.res_bits;
-      for (uint64_t r = 0; r < R; ++r) {
-        float2 v = p.root[oo + scatter(r, p.s_res, p.res_bits)];
-        acc.x += (double)v.x;
-        acc.y += (double)v.y;
+  // grid-stride: outputs beyond 2^32 / 256 workgroups (e.g. a whole state of
+  // 4^16 entries) are covered by later passes of the same threads
+  for (uint64_t o = (uint64_t)blockIdx.x * kBlock + threadIdx.x; o < n_out;
+       o += (uint64_t)gridDim.x * kBlock) {
+    const int64_t oo = scatter(o, p.s_open, p.open_bits);
+    if (p.mode == 0) {
+      double2 acc = p.out[o];
+      if (p.n_sel < 0) {
+        const uint64_t R = 1ull << p.res_bits;
+        for (uint64_t r = 0; r < R; ++r) {
+          float2 v = p.root[oo + scatter(r, p.s_res, p.res_bits)];
+          acc.x += (double)v.x;
+          acc.y += (double)v.y;
+        }
+      } else {
+        for (int i = 0; i < p.n_sel; ++i) {
+          float2 v = p.root[oo + scatter((uint64_t)p.sel_r[i], p.s_res, p.res_bits)];
+          acc.x += (double)v.x;
+          acc.y += (double)v.y;
+        }
       }
+      p.out[o] = acc;
     } else {
-      for (int i = 0; i < p.n_sel; ++i) {
-        float2 v = p.root[oo + scatter((uint64_t)p.sel_r[i], p.s_res, p.res_bits)];
-        acc.x += (double)v.x;
-        acc.y += (double)v.y;
-      }
-    }
-    p.out[o] = acc;
-  } else {
-    if (p.n_sel < 0) {
-      uint64_t R = 1ull << p.res_bits;
-      for (uint64_t r = 0; r < R; ++r) {
-        float2 v = p.root[oo + scatter(r, p.s_res, p.res_bits)];
-        int64_t row = p.row_base;
-        for (int j = 0; j < p.res_bits; ++j) row += (int64_t)((r >> j) & 1) << p.res_slicebit[j];
-        p.out[row * (int64_t)n_out + o] = make_double2(v.x, v.y);
-      }
-    } else {
-      for (int i = 0; i < p.n_sel; ++i) {
-        float2 v = p.root[oo + scatter((uint64_t)p.sel_r[i], p.s_res, p.res_bits)];
-        p.out[(int64_t)p.sel_row[i] * (int64_t)n_out + o] = make_double2(v.x, v.y);
+      if (p.n_sel < 0) {
+        const uint64_t R = 1ull << p.res_bits;
+        for (uint64_t r = 0; r < R; ++r) {
+          float2 v = p.root[oo + scatter(r, p.s_res, p.res_bits)];
+          int64_t row = p.row_base;
+          for (int j = 0; j < p.res_bits; ++j) row += (int64_t)((r >> j) & 1) << p.res_slicebit[j];
+          p.out[row * (int64_t)n_out + o] = make_double2(v.x, v.y);
+        }
+      } else {
+        for (int i = 0; i < p.n_sel; ++i) {
+          float2 v = p.root[oo + scatter((uint64_t)p.sel_r[i], p.s_res, p.res_bits)];
+          p.out[(int64_t)p.sel_row[i] * (int64_t)n_out + o] = make_double2(v.x, v.y);
+        }
       }
     }
   }

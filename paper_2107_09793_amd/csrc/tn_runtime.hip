@@ -906,7 +906,7 @@ static tn_status contract_impl(tn_plan_t plan, const void* const* leaves, const 
     sa.row_base = base;
     if (all) {
       sa.n_sel = -1;
-      hipLaunchKernelGGL(tnk::k_slice_sum, dim3(grid_for(n_out, 1u << 30)), dim3(tnk::kBlock), 0,
+      hipLaunchKernelGGL(tnk::k_slice_sum, dim3(grid_for(n_out)), dim3(tnk::kBlock), 0,
                          st, sa);
       TN_HIP_CHECK(hipGetLastError());
     } else {
@@ -918,7 +918,7 @@ static tn_status contract_impl(tn_plan_t plan, const void* const* leaves, const 
           sa.sel_r[i] = v[i0 + i].first;
           sa.sel_row[i] = v[i0 + i].second;
         }
-        hipLaunchKernelGGL(tnk::k_slice_sum, dim3(grid_for(n_out, 1u << 30)), dim3(tnk::kBlock),
+        hipLaunchKernelGGL(tnk::k_slice_sum, dim3(grid_for(n_out)), dim3(tnk::kBlock),
                            0, st, sa);
         TN_HIP_CHECK(hipGetLastError());
       }

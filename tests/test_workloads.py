@@ -41,3 +41,21 @@ def test_oracle_step_hook_prefix_and_full():
     assert seen == list(range(len(w.path)))
     assert np.array_equal(full, again)
     assert tn_oracle.contract_slice(*args, on_step=lambda k: k < 3) is None
+
+
+def test_open_output_network_is_the_state_vector():
+    """Every output index open: the contraction (any path, here the
+    time-ordered one and the greedy one) is the state vector U|0>, with the
+    open indices in qudit order (row-major state index)."""
+    import numpy as np
+    from oracle import statevector as sv
+    from oracle import tn_oracle
+    from tngen import circuits, network, path as tpath
+    for circ in (circuits.gbs_like(2, 4, 2, seed=3, d=4), circuits.grid_rqc(3, 4, 6, seed=2)):
+        tn = network.relabel_compact(network.circuit_network(circ, open_outputs=True))
+        psi = sv.final_state(circ).reshape(-1)
+        for p in (tpath.time_ordered_path(len(tn.tensors)),
+                  tpath.greedy_path(tn.labels, tn.dims, tn.open)):
+            assert tpath.check_path(len(tn.tensors), p)
+            got = tn_oracle.contract(tn.tensors, tn.labels, tn.dims, tn.open, p).reshape(-1)
+            assert np.allclose(got, psi, atol=1e-12)

@@ -59,11 +59,14 @@ class TensorNetwork:
         return True
 
 
-def circuit_network(circ, outcome=None, batch=None):
-    """Tensor network of <outcome| U |0> (``outcome``: (n,) ints) or of a batch
-    (``batch``: (B, n) ints; the batch index is open and listed in ``open``)."""
-    if (outcome is None) == (batch is None):
-        raise ValueError("give exactly one of outcome / batch")
+def circuit_network(circ, outcome=None, batch=None, open_outputs=False):
+    """Tensor network of <outcome| U |0> (``outcome``: (n,) ints), of a batch
+    (``batch``: (B, n) ints; the batch index is open and listed in ``open``),
+    or of the whole output state U|0> (``open_outputs``: every qudit's output
+    index stays open, listed in qudit order, so the result is the state in
+    the row-major order of the state vector)."""
+    if (outcome is not None) + (batch is not None) + bool(open_outputs) != 1:
+        raise ValueError("give exactly one of outcome / batch / open_outputs")
     n, d = circ.n, circ.d
     next_id = [0]
 
@@ -108,6 +111,12 @@ def circuit_network(circ, outcome=None, batch=None):
 
     tn_open = []
     batch_index = None
+    if open_outputs:
+        tn = TensorNetwork(tensors=tensors, labels=labels, dims=dict(dims),
+                           open=[wire[q] for q in range(n)], leaf_op=leaf_op,
+                           meta=dict(circuit=circ.meta))
+        tn.check()
+        return tn
     if batch is not None:
         batch = np.asarray(batch, np.int64)
         batch_index = new_id()

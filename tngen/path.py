@@ -115,3 +115,17 @@ def check_path(n, path):
         used.add(a)
         used.add(b)
     return True
+
+
+def time_ordered_path(n):
+    """The Schroedinger-style path: leaves absorbed one by one, in leaf order
+    (circuit order for networks built by ``network.circuit_network``), into
+    one running tensor, which after every gate is the state on the modes
+    reached so far.  For a network with every output open its largest
+    intermediate is the full state."""
+    if n < 2:
+        return []
+    path = [(0, 1)]
+    for k in range(1, n - 1):
+        path.append((n + k - 1, k + 1))
+    return path
