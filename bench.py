@@ -179,66 +179,102 @@ def oracle_cores():
         return len(os.sched_getaffinity(0))
 
 
-def cpu_baseline_slices(w, n_sample, gpu_per_slice):
-    """The oracle (numpy complex128, one slice at a time, no reuse) on the
-    first ``n_sample`` slices; returns its throughput and the GPU's relative
-    error on the same slices."""
-    from oracle import tn_oracle
-    n_sl = 1
-    for e in w.sliced:
-        n_sl *= w.tn.dims[e]
-    ids = list(range(min(n_sample, n_sl)))
-    t0 = time.perf_counter()
-    ref = tn_oracle.contract(w.tn.tensors, w.tn.labels, w.tn.dims, w.tn.open, w.path, w.sliced,
-                             slice_ids=ids, per_slice=True)
-    dt = time.perf_counter() - t0
-    ref = np.asarray(ref).reshape(len(ids), -1)
-    got = gpu_per_slice.reshape(gpu_per_slice.shape[0], -1)[ids]
-    rms = np.sqrt(np.mean(np.abs(ref) ** 2))
-    err = float(np.max(np.abs(got - ref)) / rms)
-    return dict(seconds=dt, cmac=None, slices=len(ids), rel_err=err,
-                sample=f"{len(ids)} whole slices")
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
-def oracle_step_costs(w):
-    """Multiply-adds of each pairwise step of one slice as the oracle runs it
-    (product of the dims of all indices of both operands, sliced ones fixed)."""
-    sl = set(w.sliced)
-    labs = {t: set(l) - sl for t, l in enumerate(w.tn.labels)}
-    opn = set(w.tn.open)
-    n = len(w.tn.labels)
-    costs = []
-    for k, (i, j) in enumerate(w.path):
+def oracle_step_costs(labels, dims, open_ids, path, fixed):
+    """Multiply-adds of each pairwise step as the oracle runs it (product of
+    the dims of all indices of both operands, the ``fixed`` ones excluded) and
+    the largest intermediate (entries)."""
+    fixed = set(fixed)
+    labs = {t: set(l) - fixed for t, l in enumerate(labels)}
+    opn = set(open_ids)
+    n = len(labels)
+    costs, big = [], 1.0
+    for k, (i, j) in enumerate(path):
         a, b = labs.pop(i), labs.pop(j)
-        costs.append(float(np.prod([w.tn.dims[x] for x in a | b], dtype=np.float64)))
+        costs.append(float(np.prod([dims[x] for x in a | b], dtype=np.float64)))
         labs[n + k] = (a | b) - ((a & b) - opn)
-    return costs
+        big = max(big, float(np.prod([dims[x] for x in labs[n + k]], dtype=np.float64)))
+    return costs, big
 
 
-def cpu_baseline_prefix(w, budget_s):
-    """The oracle on a prefix of slice 0's path: steps run in path order until
-    the next one would overrun ``budget_s`` (estimated from the rate so far)."""
+def zgemm_rate():
+    """Multiply-adds per second of numpy's complex128 matrix product here
+    (a short calibration used only to size the oracle sample)."""
+    rng = np.random.default_rng(0)
+    a = rng.standard_normal((1024, 1024)) + 1j * rng.standard_normal((1024, 1024))
+    a @ a
+    t0, reps = time.perf_counter(), 0
+    while time.perf_counter() - t0 < 0.5:
+        a @ a
+        reps += 1
+    return reps * 1024.0 ** 3 / (time.perf_counter() - t0)
+
+
+def cpu_baseline(w, budget_s, max_entries=2 ** 30):
+    """The oracle (numpy complex128, one slice at a time, no reuse) on a
+    bounded sample of the same contraction: whole slices if one fits the time
+    budget (at most 3), else one whole sub-slice of slice 0 -- every step of
+    the path, with just enough further indices fixed (chosen by the same
+    greedy slicer) that its estimated time fits the budget and its largest
+    intermediate fits host memory.  Sub-slices of a slice sum to the slice
+    (Eq. sliced_sum), so the sample is a part of the real work, large steps
+    included."""
     from oracle import tn_oracle
-    costs = oracle_step_costs(w)
-    vals = tn_oracle.decode_slice(0, [w.tn.dims[e] for e in w.sliced])
-    st = dict(done=0, cmac=0.0, t0=time.perf_counter())
-
-    def on_step(k):
-        st["done"] = k + 1
-        st["cmac"] += costs[k]
-        el = time.perf_counter() - st["t0"]
-        if k + 1 >= len(costs):
-            return True
-        rate = st["cmac"] / max(el, 1e-9)
-        return el + costs[k + 1] / rate <= budget_s
-
-    tn_oracle.contract_slice(w.tn.tensors, w.tn.labels, w.tn.open, w.path, w.sliced, vals,
-                             on_step=on_step)
-    dt = time.perf_counter() - st["t0"]
-    return dict(seconds=dt, cmac=st["cmac"], slices=None, rel_err=None,
-                sample=f"first {st['done']} of {len(costs)} steps of slice 0 "
-                       f"({st['cmac']:.3e} of {sum(costs):.3e} multiply-adds of a slice)",
-                slice_cmac=sum(costs))
+    tn, path, sliced = w.tn, w.path, list(w.sliced)
+    est_rate = 0.3 * zgemm_rate()    # the oracle's rate is below the bare product's
+    slice_cost = sum(oracle_step_costs(tn.labels, tn.dims, tn.open, path, sliced)[0])
+    n_sl = int(np.prod([tn.dims[e] for e in sliced])) if sliced else 1
+    fix = list(sliced)
+    costs, big = oracle_step_costs(tn.labels, tn.dims, tn.open, path, fix)
+    opn = set(tn.open)
+    # fix indices of the costliest step, one at a time, each the one that
+    # lowers the total most, until the sample fits the budget and memory
+    while sum(costs) / est_rate > budget_s or big > max_entries:
+        labs = {t: set(l) for t, l in enumerate(tn.labels)}
+        n = len(tn.labels)
+        worst, worst_set = -1.0, set()
+        for k, (i, j) in enumerate(path):
+            a, b = labs.pop(i), labs.pop(j)
+            if costs[k] > worst:
+                worst, worst_set = costs[k], (a | b)
+            labs[n + k] = (a | b) - ((a & b) - opn)
+        cand = [e for e in sorted(worst_set) if e not in opn and e not in fix]
+        if not cand:
+            break
+        trial = [(sum(oracle_step_costs(tn.labels, tn.dims, tn.open, path, fix + [e])[0]), e)
+                 for e in cand]
+        fix.append(min(trial)[1])
+        costs, big = oracle_step_costs(tn.labels, tn.dims, tn.open, path, fix)
+    sub = fix[len(sliced):]
+    radix = [tn.dims[e] for e in fix]
+    if not sub:
+        m = int(max(1, min(3, n_sl, budget_s // max(sum(costs) / est_rate, 1e-9))))
+        ids = list(range(m))
+        what = f"{m} whole slice{'s' if m > 1 else ''}"
+    else:
+        ids = [0]                         # slice 0, sub-slice 0 (mixed radix, first most significant)
+        n_sub = int(np.prod([tn.dims[e] for e in sub]))
+        what = (f"sub-slice 0 of {n_sub} of slice 0 ({len(sub)} more indices fixed; every "
+                f"step of the path)")
+    t0 = time.perf_counter()
+    tn_oracle.contract(tn.tensors, tn.labels, tn.dims, tn.open, path, fix, slice_ids=ids)
+    dt = time.perf_counter() - t0
+    cmac = sum(costs) * len(ids)
+    rate = cmac / dt
+    return dict(value=2.0 * rate / 1e9, unit="complex GFLOP/s", cores=oracle_cores(),
+                cpu=cpu_model(), kind="oracle",
+                sample=f"{what}: {cmac:.3e} multiply-adds ({cmac / slice_cost:.3f} of a slice "
+                       f"of {slice_cost:.3e}), numpy complex128, no reuse, {dt:.1f} s",
+                slices_per_s=rate / slice_cost, n_slices=n_sl)
 
 
 def golden(workload, seed):
@@ -403,22 +439,11 @@ def main():
                                                 "roofline", "rel_err_vs_oracle", "tolerance",
                                                 "amplitude") if k in sb}
         rec["speedup_split_bf16_vs_c64"] = r0["ms_per_step"] / sb["ms_per_step"]
+    rec["launches"] = info["n_launches"]
+    rec["us_per_amplitude"] = r0["ms_per_step"] * 1e3 / info["out_elems"]
     if args.cpu_budget > 0:
-        if info["n_slices"] > 1 and args.workload != "precision":
-            per = plan.contract(leaves, per_slice=True).cpu().numpy()
-            cb = cpu_baseline_slices(w, 3, per)
-            cmac = info["cmac_per_slice"] * cb["slices"]
-            rec["rel_err_vs_oracle"] = cb["rel_err"]
-        else:
-            cb = cpu_baseline_prefix(w, args.cpu_budget)
-            cmac = cb["cmac"]
-        rate = cmac / cb["seconds"]
-        slice_cmac = cb.get("slice_cmac", info["cmac_per_slice"])
-        rec["cpu_baseline"] = dict(value=2.0 * rate / 1e9, unit="complex GFLOP/s",
-                                   cores=oracle_cores(), kind="oracle",
-                                   sample=f"{cb['sample']}, numpy complex128, no reuse, "
-                                          f"{cb['seconds']:.1f} s",
-                                   slices_per_s=rate / slice_cmac)
+        print(f"# cpu baseline (oracle, budget {args.cpu_budget:.0f} s)", flush=True)
+        rec["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(rec), flush=True)
 
 

@@ -106,7 +106,16 @@ typedef struct {
                                  before that block's adjoint; the blocks are
                                  chosen for the least recomputation within
                                  workspace_limit)                                  */
-  int32_t reserved[4];
+  int32_t n_variable;         /* variable_leaves[n_variable]: leaves whose values may
+                                 change between calls (e.g. the output leaves of an
+                                 amplitude batch).  The steps that depend on none
+                                 of them and on no outer sliced index are the
+                                 invariant steps; their results consumed by other
+                                 steps stay in the workspace after tn_contract_ex,
+                                 so a later call with TN_CALL_REUSE_INVARIANT skips
+                                 them (Sec. 3.2 shared work, kept across calls)  */
+  const int32_t* variable_leaves;
+  int32_t reserved[2];
 } tn_plan_options;
 
 typedef enum { TN_CKPT_AUTO = 0, TN_CKPT_ALL = 1, TN_CKPT_RECOMPUTE = 2 } tn_checkpoint_policy;
@@ -148,8 +157,12 @@ typedef struct {
                                      (they depend on no outer sliced index)         */
   int32_t backward_policy;        /* TN_CKPT_ALL or TN_CKPT_RECOMPUTE (in effect)   */
   int32_t backward_blocks;        /* blocks of the backward schedule                */
-  int32_t reserved_info;
+  int32_t n_invariant;            /* schedule positions 0 .. n_invariant-1: the
+                                     invariant steps (0 without variable leaves)    */
   double cmac_backward_recompute; /* multiply-adds the backward recomputes          */
+  double cmac_invariant;          /* multiply-adds of the invariant steps           */
+  int32_t n_launches_reuse;       /* launches of a call that reuses them            */
+  int32_t reserved_info;
 } tn_plan_info;
 
 /* One step as scheduled (tests, benchmarks, autotuning). */
@@ -280,6 +293,20 @@ tn_status tn_contract_noalloc(tn_plan_t plan, const void* const* leaves,
 tn_status tn_contract_backward(tn_plan_t plan, const void* const* leaves, const void* grad_out,
                                void* const* grad_leaves, const int64_t* slice_ids,
                                int64_t n_slice_ids, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * tn_contract with call flags.  TN_CALL_REUSE_INVARIANT: the workspace holds
+ * the invariant results of an earlier tn_contract / tn_contract_ex on this
+ * plan and this workspace (same ws pointer) whose invariant leaves (all but
+ * the plan's variable leaves) had the same values; the invariant steps are
+ * not run again and their kept results are read instead.  The caller keys the
+ * reuse by the invariant leaves' contents; the library cannot check it.
+ * TN_E_INVALID if the flag is given for a plan without variable leaves.
+ */
+#define TN_CALL_REUSE_INVARIANT 1u
+tn_status tn_contract_ex(tn_plan_t plan, const void* const* leaves, const int64_t* slice_ids,
+                         int64_t n_slice_ids, int32_t out_mode, void* out, void* ws,
+                         size_t ws_bytes, void* stream, uint32_t call_flags);
 
 /*
  * tn_contract with timing of one step: ev_start / ev_stop (hipEvent_t created

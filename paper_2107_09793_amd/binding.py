@@ -39,7 +39,9 @@ class PlanOptions(ctypes.Structure):
                 ("workspace_limit", ctypes.c_int64), ("flags", ctypes.c_uint32),
                 ("gemm_config", ctypes.c_int32), ("tune", ctypes.POINTER(ctypes.c_int32)),
                 ("n_tune", ctypes.c_int32), ("checkpoint_policy", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("n_variable", ctypes.c_int32),
+                ("variable_leaves", ctypes.POINTER(ctypes.c_int32)),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -57,8 +59,9 @@ class PlanInfo(ctypes.Structure):
         [("n_chains", ctypes.c_int32), ("n_segments", ctypes.c_int32),
          ("segment_table_bytes", ctypes.c_int64), ("segment_table_offset", ctypes.c_int64),
          ("n_phase0", ctypes.c_int32), ("backward_policy", ctypes.c_int32),
-         ("backward_blocks", ctypes.c_int32), ("reserved_info", ctypes.c_int32),
-         ("cmac_backward_recompute", ctypes.c_double)]
+         ("backward_blocks", ctypes.c_int32), ("n_invariant", ctypes.c_int32),
+         ("cmac_backward_recompute", ctypes.c_double), ("cmac_invariant", ctypes.c_double),
+         ("n_launches_reuse", ctypes.c_int32), ("reserved_info", ctypes.c_int32)]
 
 
 class StepInfo(ctypes.Structure):
@@ -94,7 +97,8 @@ class SegmentLayout(ctypes.Structure):
 EXPORTS = ("tn_plan_create", "tn_plan_query", "tn_plan_step", "tn_contract",
            "tn_contract_probe", "tn_contract_backward", "tn_plan_destroy", "tn_last_error",
            "tn_permute", "tn_plan_chain", "tn_plan_schedule", "tn_plan_segment_tables",
-           "tn_contract_noalloc", "tn_plan_backward_tables")
+           "tn_contract_noalloc", "tn_plan_backward_tables", "tn_contract_ex")
+TN_CALL_REUSE_INVARIANT = 1
 NOALLOC_WORKSPACE_BYTES = 64 << 20
 
 _lib = None
@@ -119,6 +123,10 @@ def lib():
         L.tn_contract.restype = ctypes.c_int
         L.tn_contract.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_int64),
                                   ctypes.c_int64, ctypes.c_int32, P, P, ctypes.c_size_t, P]
+        L.tn_contract_ex.restype = ctypes.c_int
+        L.tn_contract_ex.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.c_int64, ctypes.c_int32, P, P, ctypes.c_size_t, P,
+                                     ctypes.c_uint32]
         L.tn_contract_probe.restype = ctypes.c_int
         L.tn_contract_probe.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_int64),
                                         ctypes.c_int64, ctypes.c_int32, P, P, ctypes.c_size_t, P,
@@ -212,7 +220,7 @@ class Plan:
                  max_resident_bits=-1, workspace_limit="auto", no_reuse=False, simple=False,
                  gemm_config=-1, tune="default", persistent=False, chains=True,
                  chain_mfma=True, chain_fused=True, chain_single=True, checkpoint="auto",
-                 fit_backward=False):
+                 fit_backward=False, variable_leaves=()):
         n_index = (max(dims) + 1) if isinstance(dims, dict) else len(dims)
         dim_arr = [dims[i] for i in range(n_index)]
         ranks, r_p = _i32([len(l) for l in labels])
@@ -235,6 +243,9 @@ class Plan:
             (TN_FLAG_FIT_BACKWARD if fit_backward else 0)
         opts.gemm_config = gemm_config
         opts.checkpoint_policy = _CKPT[checkpoint]
+        varr, v_p = _i32(list(variable_leaves) or [0])
+        opts.variable_leaves = v_p
+        opts.n_variable = len(variable_leaves)
         entries = load_tune_table() if tune == "default" else (tune or [])
         tarr, t_p = _i32([x for e in entries for x in e] or [0])
         opts.tune = t_p
@@ -253,6 +264,9 @@ class Plan:
         self.chain_valu = not chain_mfma
         self._ws = None
         self._ws_bwd = None
+        self.variable_leaves = sorted(set(int(t) for t in variable_leaves))
+        self._inv_key = None      # key of the invariant leaves whose results ws holds
+        self._inv_refs = None
 
     @classmethod
     def from_network(cls, tn, path, sliced=(), **kw):
@@ -361,6 +375,7 @@ class Plan:
         """Drop the cached device workspaces (allocated again on next use)."""
         self._ws = None
         self._ws_bwd = None
+        self._inv_key = self._inv_refs = None
 
     def _workspace(self, nbytes, device, attr):
         import torch
@@ -383,15 +398,31 @@ class Plan:
         arr = (ctypes.c_void_p * self.n_tensors)(*[x.data_ptr() for x in leaves])
         return arr, dev
 
+    def _invariant_key(self, leaves, ws):
+        """Key of the invariant leaves' contents: each tensor's identity and
+        torch's in-place version counter (the tensors are held, so their
+        storage cannot be recycled), plus the workspace."""
+        var = set(self.variable_leaves)
+        inv = [x for t, x in enumerate(leaves) if t not in var]
+        return tuple((id(x), x.data_ptr(), x._version) for x in inv) + (ws.data_ptr(),), inv
+
     def contract(self, leaves, slice_ids=None, per_slice=False, stream=None, out=None,
-                 probe=None):
+                 probe=None, reuse_invariant=True):
         """complex128 result: sum over the selected slices, or one row per slice.
         ``probe=(step, start_event, stop_event)`` times one step with the
-        given torch.cuda.Event pair (tn_contract_probe)."""
+        given torch.cuda.Event pair (tn_contract_probe).  For a plan with
+        variable leaves, the invariant steps are skipped when the invariant
+        leaves are the same tensors, unmodified, as in the previous call on
+        this workspace (``reuse_invariant``)."""
         import torch
         inf = self.info()
         arr, dev = self._leaf_ptrs(leaves)
         ws = self._workspace(inf["workspace_bytes"], dev, "_ws")
+        flags = 0
+        if self.variable_leaves and probe is None:
+            key, inv = self._invariant_key(leaves, ws)
+            if reuse_invariant and key == self._inv_key:
+                flags = TN_CALL_REUSE_INVARIANT
         shape = [self.dims[i] for i in self.open_ids]
         if slice_ids is not None:
             sids = np.ascontiguousarray(np.asarray(slice_ids, dtype=np.int64))
@@ -407,8 +438,14 @@ class Plan:
         args = (self._h, arr, sp, nsel, mode, ctypes.c_void_p(out.data_ptr()),
                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream))
         if probe is None:
-            _check(lib().tn_contract(*args))
+            if self.variable_leaves:
+                self._inv_key = None
+                _check(lib().tn_contract_ex(*args, flags))
+                self._inv_key, self._inv_refs = key, inv
+            else:
+                _check(lib().tn_contract(*args))
         else:
+            self._inv_key = None
             step, e0, e1 = probe
             for e in (e0, e1):
                 if not e.cuda_event:        # torch creates the HIP event on first record

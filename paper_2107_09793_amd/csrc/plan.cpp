@@ -584,6 +584,21 @@ static void schedule_pass(Plan& p) {
     p.node_phase[v] = (no_reuse || dep_outer) ? 1 : 0;
     S.phase = p.node_phase[v];
   }
+  // variable leaves below each node; invariant steps (group 0) depend on
+  // none of them and on no outer index
+  {
+    std::vector<uint8_t> var(nn_nodes, 0);
+    bool any = false;
+    for (int t = 0; t < n; ++t) {
+      var[t] = t < (int)p.leaf_variable.size() && p.leaf_variable[t];
+      any |= var[t] != 0;
+    }
+    for (int k = 0; k < nsteps; ++k) {
+      StepDesc& S = p.steps[k];
+      var[n + k] = var[S.a] | var[S.b];
+      S.group = S.phase == 1 ? 2 : (any && !var[n + k] ? 0 : 1);
+    }
+  }
   const int root = nn_nodes - 1;
 
   // small steps: run as work items of persistent segments (opt-in: a GPU
@@ -617,7 +632,7 @@ static void schedule_pass(Plan& p) {
       int j = k;
       ChainGroup g, cand;
       while (j + 1 < nsteps && j + 1 - k < kChainMaxSteps && fusable(j + 1) &&
-             p.steps[j + 1].a == n + j && p.steps[j + 1].phase == p.steps[k].phase &&
+             p.steps[j + 1].a == n + j && p.steps[j + 1].group == p.steps[k].group &&
              build_chain(p, lay, sbits, k, j + 1, cand)) {
         g = cand;
         ++j;
@@ -635,22 +650,24 @@ static void schedule_pass(Plan& p) {
     }
   }
 
-  // schedule: phase 0, then phase 1; inside a phase a topological order that
-  // takes every ready small step before the next ready large one (path order
-  // among equals), so small steps form long segments
+  // schedule: invariant steps, the rest of phase 0, then phase 1; inside a
+  // group a topological order that takes every ready small step before the
+  // next ready large one (path order among equals), so small steps form long
+  // segments.  (A step depending on a later group is in that group, so the
+  // order is topological.)
   std::vector<int32_t> consumer(nn_nodes, -1);
   for (int k = 0; k < nsteps; ++k) {
     consumer[p.steps[k].a] = k;
     consumer[p.steps[k].b] = k;
   }
   p.sched.clear();
-  for (int ph = 0; ph < 2; ++ph) {
+  for (int ph = 0; ph < 3; ++ph) {
     std::vector<int32_t> pending(nsteps, 0);
     std::vector<int32_t> rs, rb;   // ready small / large, kept sorted descending (pop back)
     for (int k = 0; k < nsteps; ++k) {
-      if (p.steps[k].phase != ph) continue;
+      if (p.steps[k].group != ph) continue;
       for (int x : {p.steps[k].a, p.steps[k].b})
-        if (x >= n && p.steps[x - n].phase == ph) pending[k]++;
+        if (x >= n && p.steps[x - n].group == ph) pending[k]++;
       if (pending[k] == 0) (p.steps[k].small ? rs : rb).push_back(k);
     }
     auto desc = [](std::vector<int32_t>& v) { std::sort(v.begin(), v.end(), std::greater<int32_t>()); };
@@ -661,13 +678,14 @@ static void schedule_pass(Plan& p) {
       if (!rs.empty()) { k = rs.back(); rs.pop_back(); } else { k = rb.back(); rb.pop_back(); }
       p.sched.push_back(k);
       int c = consumer[n + k];
-      if (c >= 0 && p.steps[c].phase == ph && --pending[c] == 0) {
+      if (c >= 0 && p.steps[c].group == ph && --pending[c] == 0) {
         (p.steps[c].small ? rs : rb).push_back(c);
         desc(rs);
         desc(rb);
       }
     }
-    if (ph == 0) p.n_phase0 = (int32_t)p.sched.size();
+    if (ph == 0) p.n_invariant = (int32_t)p.sched.size();
+    if (ph == 1) p.n_phase0 = (int32_t)p.sched.size();
   }
   // segments: runs of >= 2 consecutive small steps of one phase
   p.segments.clear();
@@ -675,7 +693,9 @@ static void schedule_pass(Plan& p) {
   for (size_t i = 0; i < p.sched.size();) {
     const StepDesc& S = p.steps[p.sched[i]];
     size_t j = i;
-    while (j < p.sched.size() && p.steps[p.sched[j]].small && p.steps[p.sched[j]].phase == S.phase) ++j;
+    while (j < p.sched.size() && p.steps[p.sched[j]].small &&
+           p.steps[p.sched[j]].group == S.group)
+      ++j;
     if (j - i >= 2) {
       Segment g{(int32_t)i, (int32_t)j, 0, S.phase};
       for (size_t q = i; q < j; ++q) {
@@ -723,7 +743,9 @@ static void schedule_pass(Plan& p) {
     for (int x : ins) {
       if (x < n) continue;
       const StepDesc& X = p.steps[x - n];
-      if (X.phase != S.phase) continue;
+      // results consumed by a later group stay allocated: phase-0 results
+      // for every outer iteration, invariant results for later calls
+      if (X.group != S.group) continue;
       if (seg_last[pos] >= 0) deferred.push_back({X.c_off, X.c_bytes});
       else ar.release(X.c_off, X.c_bytes);
     }
@@ -1060,8 +1082,16 @@ std::string build_plan(Plan& p, int32_t n_tensors, const int32_t* ranks,
                        const int32_t* path, int32_t n_sliced, const int32_t* sliced_ids,
                        int32_t precision, int32_t max_resident_bits, int64_t ws_limit,
                        uint32_t flags, int32_t gemm_config, const int32_t* tune, int32_t n_tune,
-                       int32_t ckpt_policy, bool* unsupported) {
+                       int32_t ckpt_policy, const int32_t* variable_leaves, int32_t n_variable,
+                       bool* unsupported) {
   *unsupported = false;
+  if (n_variable < 0 || (n_variable > 0 && !variable_leaves)) return "bad variable leaf list";
+  p.leaf_variable.assign(n_tensors > 0 ? n_tensors : 0, 0);
+  for (int32_t i = 0; i < n_variable; ++i) {
+    const int32_t t = variable_leaves[i];
+    if (t < 0 || t >= n_tensors) return "variable leaf out of range";
+    p.leaf_variable[t] = 1;
+  }
   if (ckpt_policy < CKPT_AUTO || ckpt_policy > CKPT_RECOMPUTE) return "unknown checkpoint policy";
   p.ckpt_policy = ckpt_policy;
   if (gemm_config >= kNumGemmConfigs) return "gemm_config out of range";

@@ -35,6 +35,10 @@ struct StepDesc {
   int32_t tile;           // GEMM tile configuration
   bool small = false;     // runs inside a persistent segment
   int32_t chain = -1;     // chain group this step belongs to
+  // 0: invariant (depends on no variable leaf and no outer index; its result
+  // may be kept from an earlier call), 1: rest of phase 0, 2: phase 1.
+  // Scheduled in that order; chains and segments never mix groups.
+  int32_t group = 1;
 };
 
 // A run of consecutive small steps in the schedule executed by one launch.
@@ -160,6 +164,8 @@ struct Plan {
   std::vector<StepDesc> steps;               // path order
   std::vector<int32_t> sched;                // step indices, execution order
   int32_t n_phase0 = 0;                      // sched[0 .. n_phase0) run once
+  int32_t n_invariant = 0;                   // sched[0 .. n_invariant): invariant steps
+  std::vector<uint8_t> leaf_variable;        // leaves that may change between calls
   std::vector<Segment> segments;             // persistent launches
   std::vector<ChainGroup> chains;            // fused chains of stream steps
   std::map<int32_t, std::vector<int32_t>> chain_in_low;  // chain input node -> bits to put lowest
@@ -207,6 +213,7 @@ std::string build_plan(Plan& p, int32_t n_tensors, const int32_t* ranks,
                        const int32_t* path, int32_t n_sliced, const int32_t* sliced_ids,
                        int32_t precision, int32_t max_resident_bits, int64_t ws_limit,
                        uint32_t flags, int32_t gemm_config, const int32_t* tune, int32_t n_tune,
-                       int32_t ckpt_policy, bool* unsupported);
+                       int32_t ckpt_policy, const int32_t* variable_leaves, int32_t n_variable,
+                       bool* unsupported);
 
 }  // namespace tn

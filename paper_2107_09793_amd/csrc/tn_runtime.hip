@@ -541,7 +541,8 @@ struct StagedUpload {
 
 static tn_status contract_impl(tn_plan_t plan, const void* const* leaves,
                                const int64_t* slice_ids, int64_t n_slice_ids, int32_t out_mode,
-                               void* out, void* ws, size_t ws_bytes, void* stream, Probe* probe);
+                               void* out, void* ws, size_t ws_bytes, void* stream, Probe* probe,
+                               uint32_t call_flags = 0);
 
 extern "C" {
 
@@ -566,7 +567,8 @@ tn_status tn_plan_create(int32_t n_tensors, const int32_t* ranks, const int32_t*
                                      n_open, open_ids, n_steps, path, n_sliced, sliced_ids,
                                      o.precision, o.max_resident_bits, o.workspace_limit,
                                      o.flags, o.gemm_config, o.tune, o.n_tune,
-                                     o.checkpoint_policy, &unsup);
+                                     o.checkpoint_policy, o.variable_leaves, o.n_variable,
+                                     &unsup);
     if (!err.empty()) {
       delete h;
       return fail(unsup ? TN_E_UNSUPPORTED : TN_E_INVALID, err);
@@ -620,6 +622,24 @@ tn_status tn_plan_query(tn_plan_t plan, tn_plan_info* out) {
   out->backward_policy = p.bwd.policy;
   out->backward_blocks = (int32_t)p.bwd.block_begin.size();
   out->cmac_backward_recompute = p.bwd.cmac_recompute;
+  out->n_invariant = p.n_invariant;
+  {
+    double cm = 0;
+    int32_t skipped = 0;
+    std::vector<uint8_t> chain_done(p.chains.size(), 0);
+    for (int q = 0; q < p.n_invariant; ++q) {
+      const tn::StepDesc& S = p.steps[p.sched[q]];
+      cm += S.cmac;
+      if (S.chain >= 0 && !(p.flags & 64u)) {   // one launch per fused chain
+        if (!chain_done[S.chain]) ++skipped;
+        chain_done[S.chain] = 1;
+      } else {
+        ++skipped;   // segments, split-k and multi-launch GEMM steps count once
+      }
+    }
+    out->cmac_invariant = cm;
+    out->n_launches_reuse = p.n_launches - skipped;
+  }
   return TN_OK;
 }
 
@@ -770,6 +790,13 @@ tn_status tn_contract(tn_plan_t plan, const void* const* leaves, const int64_t* 
                        nullptr);
 }
 
+tn_status tn_contract_ex(tn_plan_t plan, const void* const* leaves, const int64_t* slice_ids,
+                         int64_t n_slice_ids, int32_t out_mode, void* out, void* ws,
+                         size_t ws_bytes, void* stream, uint32_t call_flags) {
+  return contract_impl(plan, leaves, slice_ids, n_slice_ids, out_mode, out, ws, ws_bytes, stream,
+                       nullptr, call_flags);
+}
+
 tn_status tn_contract_probe(tn_plan_t plan, const void* const* leaves, const int64_t* slice_ids,
                             int64_t n_slice_ids, int32_t out_mode, void* out, void* ws,
                             size_t ws_bytes, void* stream, int32_t probe_step, void* ev_start,
@@ -789,11 +816,15 @@ tn_status tn_contract_probe(tn_plan_t plan, const void* const* leaves, const int
 
 static tn_status contract_impl(tn_plan_t plan, const void* const* leaves, const int64_t* slice_ids,
                         int64_t n_slice_ids, int32_t out_mode, void* out, void* ws,
-                        size_t ws_bytes, void* stream, Probe* probe) {
+                        size_t ws_bytes, void* stream, Probe* probe, uint32_t call_flags) {
   if (!plan || !leaves || !out) return fail(TN_E_INVALID, "NULL argument");
   const tn::Plan& p = plan->p;
   if (out_mode != TN_OUT_SUM && out_mode != TN_OUT_PER_SLICE)
     return fail(TN_E_INVALID, "unknown out_mode");
+  if ((call_flags & ~TN_CALL_REUSE_INVARIANT) != 0) return fail(TN_E_INVALID, "unknown call flag");
+  if ((call_flags & TN_CALL_REUSE_INVARIANT) &&
+      std::find(p.leaf_variable.begin(), p.leaf_variable.end(), 1) == p.leaf_variable.end())
+    return fail(TN_E_INVALID, "TN_CALL_REUSE_INVARIANT needs a plan with variable leaves");
   if ((int64_t)ws_bytes < p.workspace_bytes || (!ws && p.workspace_bytes > 0))
     return fail(TN_E_WORKSPACE, "workspace smaller than tn_plan_info.workspace_bytes");
   if (n_slice_ids < 0 || (n_slice_ids > 0 && !slice_ids))
@@ -874,9 +905,11 @@ static tn_status contract_impl(tn_plan_t plan, const void* const* leaves, const 
     }
     return TN_OK;
   };
-  // shared work: steps that depend on no outer index, once
+  // shared work: steps that depend on no outer index, once (the invariant
+  // ones only if their results are not kept from an earlier call)
   {
-    tn_status s = run_range(0, p.n_phase0, 0);
+    const bool reuse = (call_flags & TN_CALL_REUSE_INVARIANT) != 0;
+    tn_status s = run_range(reuse ? p.n_invariant : 0, p.n_phase0, 0);
     if (s != TN_OK) return s;
   }
   const uint64_t n_it = 1ull << p.outer_bits;

@@ -43,13 +43,17 @@ def _chain(ch, X, x0, Bs, Y, y0, dtype):
         buf[:, bit_offsets(ch["out_slot"])]
 
 
-def execute(plan, leaves, dtype=np.complex128):
+def execute(plan, leaves, dtype=np.complex128, arena=None, start=0):
+    """Runs the schedule from position ``start`` (earlier results are read
+    from ``arena``, as left by a previous run: the reuse of invariant
+    results).  Returns (sum over resident slices, per-slice values, arena)."""
     info = plan.info()
     if info["n_outer_bits"] != 0:
         raise NotImplementedError("CPU executor handles all-resident plans only")
     n = plan.n_tensors
     steps = plan.steps()
-    arena = np.full(max(info["arena_bytes"] // 8, 1), np.nan + 0j, dtype=dtype)
+    if arena is None:
+        arena = np.full(max(info["arena_bytes"] // 8, 1), np.nan + 0j, dtype=dtype)
     flat = [np.asarray(x, dtype).reshape(-1) for x in leaves]
 
     def src(node):
@@ -58,8 +62,7 @@ def execute(plan, leaves, dtype=np.complex128):
         return arena, steps[node - n]["c_offset"] // 8
 
     chains = plan.chains() if info.get("n_chains", 0) else []
-    order = [k for k in range(n - 1) if steps[k]["phase"] == 0] + \
-            [k for k in range(n - 1) if steps[k]["phase"] == 1]
+    order = plan.schedule()[start:]
     for k in order:
         s = steps[k]
         stepwise = s["chain"] >= 0 and steps[chains[s["chain"]]["first"]]["c_offset"] != -1 \
@@ -92,7 +95,7 @@ def execute(plan, leaves, dtype=np.complex128):
     oo = bit_offsets(info["root_open_log2"][:info["n_open_bits"]])
     orr = bit_offsets(info["root_res_log2"][:info["n_resident_bits"]])
     vals = root[r0 + oo[:, None] + orr[None, :]]
-    return vals.sum(1), vals
+    return vals.sum(1), vals, arena
 
 
 def leaf_outer_offsets(plan, tn):

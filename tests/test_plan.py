@@ -146,7 +146,7 @@ def test_cpu_execution_of_plan_matches_oracle(case):
         ts = slicing.TreeSets(labels, dims, open_ids, path)
         sl = slicing.greedy_slices(ts, n_slice=ns) if ns else []
     pl = Plan(labels, dims, open_ids, path, sl)
-    got, per = execute(pl, tensors)
+    got, per, _ = execute(pl, tensors)
     ref = tn_oracle.contract(tensors, labels, dims, open_ids, path, sl)
     ref = np.asarray(ref).reshape(-1)
     assert np.allclose(got, ref, rtol=1e-12, atol=1e-14 * np.max(np.abs(ref)))
@@ -198,20 +198,20 @@ def test_cpu_execution_of_fused_chains_matches_oracle(cfg):
             return 2 * 2 ** (nk + nn)
         used = sum(staged(d) for d in ch["st"])
         assert used <= 4096
-    got, _ = execute(pl, tn.tensors)
+    got, _, _ = execute(pl, tn.tensors)
     ref = np.asarray(tn_oracle.contract(tn.tensors, tn.labels, tn.dims, tn.open, p, sl)).reshape(-1)
     assert np.allclose(got, ref, rtol=1e-12, atol=1e-13 * np.max(np.abs(ref)))
     stepwise = Plan.from_network(tn, p, sl, chain_fused=False)
     assert stepwise.info()["n_chains"] == info["n_chains"]
     assert all(s["c_offset"] >= 0 for s in stepwise.steps())
-    got2, _ = execute(stepwise, tn.tensors)
+    got2, _, _ = execute(stepwise, tn.tensors)
     assert np.allclose(got2, ref, rtol=1e-12, atol=1e-13 * np.max(np.abs(ref)))
     # lone chainable steps run as one-step chains unless switched off
     multi = Plan.from_network(tn, p, sl, chain_single=False)
     mch = multi.chains()
     assert all(len(ch["st"]) >= 2 for ch in mch)
     assert len(mch) == sum(len(ch["st"]) >= 2 for ch in chains)
-    got3, _ = execute(multi, tn.tensors)
+    got3, _, _ = execute(multi, tn.tensors)
     assert np.allclose(got3, ref, rtol=1e-12, atol=1e-13 * np.max(np.abs(ref)))
     unfused = Plan.from_network(tn, p, sl, persistent=False, chains=False)
     assert unfused.info()["n_chains"] == 0
@@ -252,7 +252,7 @@ def test_chain_descriptors_hold_wide_matrix_core_steps():
     for ch in valu.chains():
         for d in ch["st"]:
             assert vsteps[d["step"]]["nk"] <= 4 and vsteps[d["step"]]["nn"] <= 4
-    got, _ = execute(pl, tn.tensors)
+    got, _, _ = execute(pl, tn.tensors)
     ref = np.asarray(tn_oracle.contract(tn.tensors, tn.labels, tn.dims, tn.open, p, sl)).reshape(-1)
     assert np.allclose(got, ref, rtol=1e-12, atol=1e-13 * np.max(np.abs(ref)))
 
@@ -339,3 +339,51 @@ def test_workspace_too_small_is_reported():
                                 ctypes.c_void_p(0x3000), info["workspace_backward_bytes"] - 1,
                                 None)
     assert st == binding.TN_E_WORKSPACE
+
+
+@pytest.mark.parametrize("batch", [None, 8])
+def test_invariant_results_reused_across_calls(batch):
+    """Variable leaves (the output leaves): the steps depending on none of
+    them run first; their results consumed later stay in the arena, so a
+    second run from position n_invariant with new output leaves reuses them
+    (Sec. 3.2, shared work kept across amplitudes).  The reused run ignores
+    the leaves only invariant steps read (they are zeroed here), which shows
+    the invariant steps really are skipped."""
+    circ = circuits.grid_rqc(3, 4, 8, seed=4)
+    outs = circuits.random_bitstrings(circ.n, 2, 3 * (batch or 1), 4)
+    nets = []
+    for i in range(3):
+        if batch:
+            tn = network.circuit_network(circ, batch=outs[i * batch:(i + 1) * batch])
+        else:
+            tn = network.circuit_network(circ, outcome=outs[i])
+        nets.append(network.relabel_compact(tn))
+    tn = nets[0]
+    p = tpath.greedy_path(tn.labels, tn.dims, tn.open)
+    sl = slicing.greedy_slices(slicing.TreeSets(tn.labels, tn.dims, tn.open, p), n_slice=3)
+    var = tn.meta["output_leaves"]
+    pl = Plan(tn.labels, tn.dims, tn.open, p, sl, variable_leaves=var)
+    info = pl.info()
+    steps, sched = pl.steps(), pl.schedule()
+    n = pl.n_tensors
+    below = [set() for _ in range(2 * n - 1)]
+    for t in range(n):
+        below[t] = {t}
+    for k, s in enumerate(steps):
+        below[n + k] = below[s["a"]] | below[s["b"]]
+    inv = [k for k in range(n - 1) if not below[n + k] & set(var)]
+    assert sorted(sched[:info["n_invariant"]]) == sorted(inv) and 0 < len(inv) < n - 1
+    assert info["n_launches_reuse"] < info["n_launches"]
+    got, _, arena = execute(pl, tn.tensors)
+    ref = tn_oracle.contract(tn.tensors, tn.labels, tn.dims, tn.open, p, sl)
+    assert np.allclose(got, np.asarray(ref).reshape(-1), rtol=1e-12)
+    inv_set = set(inv)
+    only_inv = [t for t in range(n)
+                if any(k in inv_set for k, s in enumerate(steps) if t in (s["a"], s["b"]))]
+    assert only_inv
+    for other in nets[1:]:
+        assert other.labels == tn.labels
+        leaves = [np.zeros_like(x) if t in only_inv else x for t, x in enumerate(other.tensors)]
+        got, _, arena = execute(pl, leaves, arena=arena, start=info["n_invariant"])
+        ref = tn_oracle.contract(other.tensors, tn.labels, tn.dims, tn.open, p, sl)
+        assert np.allclose(got, np.asarray(ref).reshape(-1), rtol=1e-12)

@@ -114,7 +114,7 @@ def circuit_network(circ, outcome=None, batch=None, open_outputs=False):
     if open_outputs:
         tn = TensorNetwork(tensors=tensors, labels=labels, dims=dict(dims),
                            open=[wire[q] for q in range(n)], leaf_op=leaf_op,
-                           meta=dict(circuit=circ.meta))
+                           meta=dict(circuit=circ.meta, output_leaves=sorted(per_tensor)))
         tn.check()
         return tn
     if batch is not None:
@@ -142,7 +142,7 @@ def circuit_network(circ, outcome=None, batch=None, open_outputs=False):
     dims = {i: dims[i] for i in used}
     tn = TensorNetwork(tensors=tensors, labels=labels, dims=dims, open=tn_open,
                        leaf_op=leaf_op, batch_index=batch_index,
-                       meta=dict(circuit=circ.meta))
+                       meta=dict(circuit=circ.meta, output_leaves=sorted(per_tensor)))
     tn.check()
     return tn
 
