@@ -184,7 +184,9 @@ typedef struct {
                                  stays inside a fused chain and is never stored)  */
   int64_t c_bytes;
   int32_t chain;              /* fused chain holding the step, or -1              */
-  int32_t reserved;
+  int32_t chunks;             /* split-k kernels and GEMM steps split over k: chunks
+                                 of the summed bits, added up in a fixed order (1:
+                                 no split)                                          */
 } tn_step_info;
 
 /* One fused chain as planned (tests).  A chain runs steps first..last (path

@@ -41,6 +41,11 @@ struct GemmArgs {
   // logical tile of workgroup 0: steps with more tiles than one dispatch can
   // hold (2^32 work-items) run as several launches over consecutive ranges
   uint64_t tile0;
+  // split k (few output tiles, long sums): 2^kc_log2 chunks of the k tiles,
+  // chunk c of every output tile is logical tile c * ntiles + tile and writes
+  // its partial result at C + c * part_stride (the reduce adds them up)
+  int32_t kc_log2;
+  int64_t part_stride;
 };
 
 template <int V>
@@ -143,6 +148,8 @@ struct GemmCommon {
   static constexpr int AE = MT * KT / 256, BE = NT * KT / 256;
   int64_t baseA, baseB, baseC, kA, kB;
   uint64_t gray, nkt, ntiles, tile;
+  int kc_log2;
+  int64_t part_stride, cpart;
   OffT a_go[AE], b_go[BE];   // in-tile offsets (32-bit when they fit)
   int a_mk[AE], b_nk[BE];    // packed LDS coordinates: row/col | k << 16
   uint32_t a_ok, b_ok;
@@ -171,7 +178,9 @@ struct GemmCommon {
       b_go[r] = (OffT)(t.bn[ni] + t.bk[ki]);
       if (ni < nlim && ki < klim) b_ok |= 1u << r;
     }
-    nkt = 1ull << (p.nk > LK ? p.nk - LK : 0);
+    kc_log2 = g.kc_log2;
+    part_stride = g.part_stride;
+    nkt = 1ull << ((p.nk > LK ? p.nk - LK : 0) - kc_log2);   // k tiles per chunk
     int lnt = p.nn > LN ? p.nn - LN : 0;
     int lmt = p.nm > LM ? p.nm - LM : 0;
     ntiles = 1ull << (p.nb + lmt + lnt);
@@ -181,12 +190,18 @@ struct GemmCommon {
 
   __device__ __forceinline__ void set_tile(const StepArgs& p, const Strides& S, uint64_t t) {
     uint64_t bidx, mt, nt;
+    const uint64_t chunk = t / ntiles;   // split k: the chunk is the slowest index
+    t -= chunk * ntiles;
     tile_coords(p, LM, LN, t, ntiles, remap, bidx, mt, nt);
     baseA = scatter_range(mt << LM, S.Am(), LM, p.nm) + scatter(bidx, S.Ab(), p.nb);
     baseB = scatter_range(nt << LN, S.Bn(), LN, p.nn) + scatter(bidx, S.Bb(), p.nb);
     baseC = scatter_range(mt << LM, S.Cm(), LM, p.nm) + scatter_range(nt << LN, S.Cn(), LN, p.nn) +
-            scatter(bidx, S.Cb(), p.nb);
-    kA = kB = 0;
+            scatter(bidx, S.Cb(), p.nb) + (int64_t)chunk * part_stride;
+    // the chunk's k tiles share their high k bits; the walk below covers the
+    // low ones in Gray order from this base
+    const int lk_lo = LK + (p.nk > LK ? p.nk - LK : 0) - kc_log2;
+    kA = scatter_range(chunk << lk_lo, S.Ak(), lk_lo, p.nk);
+    kB = scatter_range(chunk << lk_lo, S.Bk(), lk_lo, p.nk);
     gray = 0;
   }
 
@@ -249,7 +264,7 @@ __device__ __forceinline__ void gemm_tiles(const StepArgs& p, const Strides& S,
                                            const GemmTables<MT, NT, KT>& tab, Ops& ops) {
   using GC = GemmCommon<MT, NT, KT, OffT>;
   const uint64_t tile = c.tile;
-  if (tile >= c.ntiles) return;
+  if (tile >= c.ntiles << c.kc_log2) return;
   float2 ra[GC::AE], rb[GC::BE];
   floatx16 acc[WM][WN];
   c.set_tile(p, S, tile);
@@ -475,6 +490,29 @@ __global__ void __launch_bounds__(256) k_gemm_sb16(GemmArgs g) {
   ops.wave_m = (threadIdx.x >> 6) / WVN;
   ops.wave_n = (threadIdx.x >> 6) % WVN;
   gemm_tiles<WVN, WM, WN>(p, S, c, tab, ops);
+}
+
+// Sum of the split-k partial tiles of a GEMM step: partial c holds the
+// chunk's result at the result's own offsets plus c * n_out (the result is a
+// dense layout of n_out entries), added in chunk order in float64.
+__global__ void __launch_bounds__(256) k_gemm_splitk_reduce(float2* C, const float2* part,
+                                                            int64_t n_out, int32_t nchunk,
+                                                            int32_t accumulate) {
+  for (int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x; o < n_out;
+       o += (int64_t)gridDim.x * 256) {
+    double re = 0.0, im = 0.0;
+    for (int32_t c = 0; c < nchunk; ++c) {
+      const float2 v = part[(int64_t)c * n_out + o];
+      re += v.x;
+      im += v.y;
+    }
+    if (accumulate) {
+      const float2 v = C[o];
+      re += v.x;
+      im += v.y;
+    }
+    C[o] = make_float2((float)re, (float)im);
+  }
 }
 
 }  // namespace tnk

@@ -398,6 +398,16 @@ int32_t choose_kind(int nb, int nm, int nn, int nk, uint32_t flags, int32_t* chu
   *chunks = 0;
   *scratch = 0;
   if (nk >= 8 && out_bits <= 12) {
+    if (nm >= 5 && nn >= 3 && !(flags & 2u)) {
+      // few output tiles, long sums: MFMA tiles over chunks of k (about 2^11
+      // workgroups in all, at least one 32-wide k tile per chunk), partial
+      // tiles added up in a fixed order afterwards
+      const int tiles_log2 = std::max(0, out_bits - 12);
+      const int cl = std::max(0, std::min(11 - tiles_log2, nk - 5));
+      *chunks = 1 << cl;
+      *scratch = cl > 0 ? (int64_t)8 << (out_bits + cl) : 0;
+      return KIND_GEMM;
+    }
     int cl = std::max(8, nk - 10);  // log2 chunk length
     if (cl > nk) cl = nk;
     *chunks = 1 << (nk - cl);
@@ -436,6 +446,7 @@ int32_t choose_tile(const Plan& p, int nm, int nn, int nk) {
 // than 2^32 work-items of 256-thread workgroups).
 static int32_t step_launches(const StepDesc& S) {
   if (S.kind == KIND_SPLITK) return 2;
+  if (S.kind == KIND_GEMM && S.splitk_chunks > 1) return 2;   // partial tiles, then their sum
   if (S.kind != KIND_GEMM || S.tile < 0 || S.tile >= kNumGemmConfigs) return 1;
   static const int lm[kNumGemmConfigs] = {7, 7, 8, 7, 8, 7, 7, 7};   // log2 tile rows
   static const int ln[kNumGemmConfigs] = {6, 5, 4, 7, 6, 6, 5, 4};   // log2 tile columns

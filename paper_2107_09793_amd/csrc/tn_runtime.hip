@@ -182,7 +182,8 @@ void launch_tiles(uint64_t ntiles, const tnk::GemmArgs& g0, hipStream_t st) {
 }
 
 template <int WVM, int WVN, int WM, int WN, int LK>
-tn_status launch_gemm_cfg(const tnk::StepArgs& a, int32_t precision, hipStream_t st) {
+tn_status launch_gemm_cfg(const tnk::StepArgs& a, int32_t precision, hipStream_t st,
+                          int32_t chunks, float2* scratch) {
   constexpr int MT = WVM * WM * 32, NT = WVN * WN * 16;
   constexpr int LM = tnk::ilog2<MT>::value, LN = tnk::ilog2<NT>::value;
   // split-BF16 tiles always walk k by 16
@@ -194,29 +195,46 @@ tn_status launch_gemm_cfg(const tnk::StepArgs& a, int32_t precision, hipStream_t
   g.b_mask = tile_mask(LN, a.sB_n, a.nn, lk, a.sB_k, a.nk);
   int lmt = a.nm > LM ? a.nm - LM : 0, lnt = a.nn > LN ? a.nn - LN : 0;
   uint64_t ntiles = 1ull << (a.nb + lmt + lnt);
-  g.xcd_remap = ntiles >= 64 ? 1 : 0;
+  // split k: chunks of the k tiles write partial tiles into the scratch
+  // area, which k_gemm_splitk_reduce adds up into C
+  int kc = 0;
+  while ((1 << (kc + 1)) <= chunks && kc + 1 <= a.nk - lk) ++kc;
+  const int64_t n_out = (int64_t)1 << (a.nb + a.nm + a.nn);
+  if (kc > 0) {
+    if (!scratch) return fail(TN_E_INVALID, "split-k GEMM step without scratch");
+    g.kc_log2 = kc;
+    g.part_stride = n_out;
+    g.s.C = scratch;
+    g.s.accumulate = 0;
+  }
+  g.xcd_remap = (kc == 0 && ntiles >= 64) ? 1 : 0;
+  const uint64_t nwg = ntiles << kc;
   const bool small = max_tile_offset(LM, a.sA_m, a.nm, lk, a.sA_k, a.nk) < (1ll << 31) &&
                      max_tile_offset(LN, a.sB_n, a.nn, lk, a.sB_k, a.nk) < (1ll << 31);
   if (precision == tn::PREC_SPLIT_BF16) {
-    if (small) launch_tiles<tnk::k_gemm_sb16<WVM, WVN, WM, WN, int32_t>>(ntiles, g, st);
-    else launch_tiles<tnk::k_gemm_sb16<WVM, WVN, WM, WN, int64_t>>(ntiles, g, st);
+    if (small) launch_tiles<tnk::k_gemm_sb16<WVM, WVN, WM, WN, int32_t>>(nwg, g, st);
+    else launch_tiles<tnk::k_gemm_sb16<WVM, WVN, WM, WN, int64_t>>(nwg, g, st);
   } else {
-    if (small) launch_tiles<tnk::k_gemm_c64<WVM, WVN, WM, WN, LK, int32_t>>(ntiles, g, st);
-    else launch_tiles<tnk::k_gemm_c64<WVM, WVN, WM, WN, LK, int64_t>>(ntiles, g, st);
+    if (small) launch_tiles<tnk::k_gemm_c64<WVM, WVN, WM, WN, LK, int32_t>>(nwg, g, st);
+    else launch_tiles<tnk::k_gemm_c64<WVM, WVN, WM, WN, LK, int64_t>>(nwg, g, st);
   }
+  if (kc > 0)
+    hipLaunchKernelGGL(tnk::k_gemm_splitk_reduce, dim3(grid_for((uint64_t)n_out)), dim3(256), 0,
+                       st, a.C, scratch, n_out, (int32_t)(1 << kc), a.accumulate);
   return TN_OK;
 }
 
-tn_status launch_gemm(const tnk::StepArgs& a, int32_t precision, int32_t tile, hipStream_t st) {
+tn_status launch_gemm(const tnk::StepArgs& a, int32_t precision, int32_t tile, hipStream_t st,
+                      int32_t chunks, float2* scratch) {
   switch (tile) {
-    case 0: return launch_gemm_cfg<2, 2, 2, 2, 4>(a, precision, st);   // 128 x 64
-    case 1: return launch_gemm_cfg<4, 1, 1, 2, 4>(a, precision, st);   // 128 x 32
-    case 2: return launch_gemm_cfg<4, 1, 2, 1, 4>(a, precision, st);   // 256 x 16
-    case 3: return launch_gemm_cfg<2, 2, 2, 4, 4>(a, precision, st);   // 128 x 128
-    case 4: return launch_gemm_cfg<2, 2, 4, 2, 4>(a, precision, st);   // 256 x 64
-    case 5: return launch_gemm_cfg<2, 2, 2, 2, 5>(a, precision, st);   // 128 x 64, k tile 32
-    case 6: return launch_gemm_cfg<4, 1, 1, 2, 3>(a, precision, st);   // 128 x 32, k tile 8
-    case 7: return launch_gemm_cfg<4, 1, 1, 1, 4>(a, precision, st);   // 128 x 16
+    case 0: return launch_gemm_cfg<2, 2, 2, 2, 4>(a, precision, st, chunks, scratch);   // 128 x 64
+    case 1: return launch_gemm_cfg<4, 1, 1, 2, 4>(a, precision, st, chunks, scratch);   // 128 x 32
+    case 2: return launch_gemm_cfg<4, 1, 2, 1, 4>(a, precision, st, chunks, scratch);   // 256 x 16
+    case 3: return launch_gemm_cfg<2, 2, 2, 4, 4>(a, precision, st, chunks, scratch);   // 128 x 128
+    case 4: return launch_gemm_cfg<2, 2, 4, 2, 4>(a, precision, st, chunks, scratch);   // 256 x 64
+    case 5: return launch_gemm_cfg<2, 2, 2, 2, 5>(a, precision, st, chunks, scratch);   // 128 x 64, k tile 32
+    case 6: return launch_gemm_cfg<4, 1, 1, 2, 3>(a, precision, st, chunks, scratch);   // 128 x 32, k tile 8
+    case 7: return launch_gemm_cfg<4, 1, 1, 1, 4>(a, precision, st, chunks, scratch);   // 128 x 16
     default: return fail(TN_E_INVALID, "unknown GEMM tile configuration");
   }
 }
@@ -240,7 +258,7 @@ tn_status launch_step(int32_t kind, int32_t chunks, int32_t tile, const tnk::Ste
   } else if (kind == tn::KIND_STREAM && a.nk <= 4 && a.nn <= 4) {
     launch_stream(a, st);
   } else if (kind == tn::KIND_GEMM) {
-    tn_status s = launch_gemm(a, precision, tile, st);
+    tn_status s = launch_gemm(a, precision, tile, st, chunks, scratch);
     if (s != TN_OK) return s;
   } else {
     hipLaunchKernelGGL(tnk::k_simple, dim3(grid_for(n_out)), dim3(tnk::kBlock), 0, st, a);
@@ -673,6 +691,7 @@ tn_status tn_plan_step(tn_plan_t plan, int32_t step, tn_step_info* out) {
   out->c_offset = S.c_off;
   out->c_bytes = S.c_bytes;
   out->chain = S.chain;
+  out->chunks = S.splitk_chunks > 1 ? S.splitk_chunks : 1;
   return TN_OK;
 }
 

@@ -54,6 +54,9 @@ CASES = [
     (2, 10, 2, 4, 1, "stream"),
     (3, 4, 2, 3, 0, "stream"),     # batch bits inside a workgroup's rows: B through the cache
     (0, 7, 4, 4, 0, "stream"),     # fewer rows than a workgroup
+    (1, 6, 5, 14, 0, "gemm"),      # few output tiles, long sums: MFMA tiles split over k
+    (0, 5, 3, 12, 0, "gemm"),      # ... with partial tiles
+    (0, 7, 4, 9, 1, "gemm"),       # ... dim-4 rows
     (0, 2, 2, 14, 0, "splitk"),
     (3, 1, 0, 10, 0, "splitk"),
     (0, 3, 3, 6, 0, "simple"),
@@ -72,6 +75,8 @@ def test_pairwise_kernels(case, precision):
     pl = Plan(labels, dims, open_ids, [(0, 1)], precision=precision)
     st = pl.step(0)
     assert st["kind_name"] == kind, st["kind_name"]
+    if kind == "gemm":   # split over k: long sums, few outputs
+        assert (st["chunks"] > 1) == (nk >= 8 and nb + nm + nn + d4 <= 12), st["chunks"]
     dev = torch.device("cuda:0")
     leaves = [torch.from_numpy(t.astype(np.complex64)).to(dev) for t in tensors]
     got = pl.contract(leaves).cpu().numpy()
@@ -85,12 +90,14 @@ def test_pairwise_kernels(case, precision):
         assert err <= 1e-4  # three-product split: ~2^-16 relative
 
 
-def test_gemm_deterministic_run_to_run():
+@pytest.mark.parametrize("shape", [(1, 10, 7, 6), (1, 6, 5, 14)])
+def test_gemm_deterministic_run_to_run(shape):
+    """Tiles, and partial tiles of a split sum added in a fixed order."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2107_09793_amd import Plan
     rng = np.random.default_rng(3)
-    tensors, labels, dims, open_ids = _case(rng, 1, 10, 7, 8)
+    tensors, labels, dims, open_ids = _case(rng, *shape)
     pl = Plan(labels, dims, open_ids, [(0, 1)])
     dev = torch.device("cuda:0")
     leaves = [torch.from_numpy(t.astype(np.complex64)).to(dev) for t in tensors]
@@ -107,7 +114,7 @@ def test_every_gemm_tile_config(cfg, precision):
         pytest.skip("no GPU")
     from paper_2107_09793_amd import Plan
     dev = torch.device("cuda:0")
-    for shape in ((1, 10, 8, 7, 0), (0, 6, 5, 5, 1)):
+    for shape in ((1, 10, 8, 7, 0), (0, 6, 5, 5, 1), (0, 6, 5, 12, 0)):
         rng = np.random.default_rng([cfg, *shape])
         tensors, labels, dims, open_ids = _case(rng, *shape)
         pl = Plan(labels, dims, open_ids, [(0, 1)], precision=precision, gemm_config=cfg)
