@@ -277,13 +277,25 @@ def cpu_baseline(w, budget_s, max_entries=2 ** 30):
                 slices_per_s=rate / slice_cost, n_slices=n_sl)
 
 
-def golden(workload, seed):
-    """complex128 oracle values of sampled slices, written by
-    tests/golden/make_precision_slices.py (oracle only), or None."""
+def path_fingerprint(w):
+    """Hash of the path and the sliced indices (as the scripts that write the
+    stored oracle values compute it)."""
+    import hashlib
+    h = hashlib.sha256()
+    h.update(json.dumps([list(map(int, p)) for p in w.path]).encode())
+    h.update(json.dumps(list(map(int, w.sliced))).encode())
+    return h.hexdigest()[:16]
+
+
+def golden(workload, seed, w):
+    """complex128 oracle values of sampled slices of this very path and slice
+    set, written by the scripts in tests/golden/ (oracle only), or None."""
     path = os.path.join(ROOT, "tests", "golden", f"{workload}_slices_seed{seed}.json")
     if not os.path.exists(path):
         return None
     doc = json.load(open(path))
+    if doc.get("fingerprint") != path_fingerprint(w):
+        return None
     return [s[0] for s in doc["slices"]], np.array([s[1] + 1j * s[2] for s in doc["slices"]])
 
 
@@ -360,7 +372,7 @@ def run_precision(args, w, precision, leaves, torch, ws_limit):
                          cmac_exec=info["cmac_exec"], f_sl=info["f_sl"],
                          arena_bytes=info["arena_bytes"], n_launches=info["n_launches"],
                          n_steps=info["n_steps"], outer_bits=info["n_outer_bits"]))
-    gold = golden(args.workload, args.seed)
+    gold = golden(args.workload, args.seed, w)
     if gold is not None:
         ids, ref = gold
         got = plan.contract(leaves, slice_ids=ids, per_slice=True).cpu().numpy().reshape(-1)
@@ -383,6 +395,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0,
                     help="seconds of oracle work for cpu_baseline (0 = skip)")
     ap.add_argument("--no-reuse", action="store_true")
+    ap.add_argument("--path", default="default", choices=["default", "greedy", "cmac", "time"],
+                    help="contraction path: the workload's default, the seeded greedy "
+                         "search alone, or followed by the shared-work-aware refinement "
+                         "(multiply-adds with reuse; then the roofline time estimate)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): slices are independent, "
@@ -396,7 +412,8 @@ def main():
     from tngen import workloads
 
     dev = torch.device("cuda:0")
-    w = workloads.build(args.workload, seed=args.seed)
+    w = workloads.build(args.workload, seed=args.seed,
+                        refine={"default": None, "greedy": False}.get(args.path, args.path))
     leaves = [torch.from_numpy(np.ascontiguousarray(t, dtype=np.complex64)).to(dev)
               for t in w.tn.tensors]
     perm = permute_roofline(torch)

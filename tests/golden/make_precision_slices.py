@@ -3,9 +3,11 @@ slices of the 53-qubit depth-12 workload (seed 0).
 
 Calls only the oracle (tn_oracle.contract) on inputs from the seeded
 generators.  Each requested slice is contracted as the sum of its 4
-sub-slices over two further sliced indices (picked by the same greedy
-slicer), which bounds host memory; the sum of sub-slices is exactly the slice
-(Eq. sliced_sum).
+sub-slices over two further sliced indices, which bounds host memory; the
+sum of sub-slices is exactly the slice (Eq. sliced_sum).  The two indices
+are the pair, among the indices of the per-slice intermediates of 2^28 or
+more entries, with the smallest (largest sub-slice intermediate, sub-slice
+multiply-adds).
 
     python tests/golden/make_precision_slices.py [slice ids ...]
 
@@ -35,6 +37,24 @@ def fingerprint(w):
     return h.hexdigest()[:16]
 
 
+def extra_pair(ts, base):
+    col = {i: c for c, i in enumerate(ts.ids)}
+    s0 = np.zeros(len(ts.ids), bool)
+    for i in base:
+        s0[col[i]] = True
+    node = (ts.open[ts.n:] * (ts.w - ts.w * s0)).sum(1)
+    big = np.where(node >= 28)[0]
+    cand = sorted(set(np.where(ts.open[ts.n:][big].any(0) & ~ts.kept & ~s0)[0]))
+    best = None
+    for i, a in enumerate(cand):
+        for b in cand[i + 1:]:
+            st = ts.stats(base + [ts.ids[a], ts.ids[b]])
+            key = (st["max_log2"], st["flop_sl"], a, b)
+            if best is None or key < best:
+                best = key
+    return [ts.ids[best[2]], ts.ids[best[3]]]
+
+
 def default_ids():
     fixed = [0, 1, 513, 1023]
     rest = np.setdiff1d(np.arange(1024), fixed)
@@ -46,9 +66,7 @@ def main():
     ids = [int(x) for x in sys.argv[1:]] or default_ids()
     w = workloads.build("precision", seed=0)
     ts = slicing.TreeSets(w.tn.labels, w.tn.dims, w.tn.open, w.path)
-    ext = slicing.greedy_slices(ts, n_slice=len(w.sliced) + 2)
-    assert ext[:len(w.sliced)] == list(w.sliced)
-    extra = ext[len(w.sliced):]
+    extra = extra_pair(ts, list(w.sliced))
     n_sub = int(np.prod([w.tn.dims[e] for e in extra]))
     out = []
     for sid in ids:

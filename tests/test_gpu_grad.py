@@ -9,9 +9,12 @@
    circuit (4x5 grid, depth 10, 256 outcomes) through Amplitude.apply and
    torch autograd, against the state-vector adjoint (complex128) and central
    finite differences (h = 1e-4, float64).
-Tolerance: the stated complex64 tolerance, 1e-5: relative for leaf
-gradients (directional), norm-wise for the parameter gradient, and per
-parameter (relative to max(1, |gradient|)) against finite differences.
+Tolerance: the stated complex64 tolerance, 1e-5 (1e-3 for split-BF16),
+norm-wise: a directional derivative sum(conj(g) * D) is compared within
+tol * ||g|| ||D|| (the Cauchy-Schwarz bound of the inner product, so a result
+that cancels is not judged against its own small size), the parameter
+gradient within tol of its norm, and each checked parameter against finite
+differences within tol * max(1, |gradient|).
 """
 
 import numpy as np
@@ -70,7 +73,8 @@ def test_leaf_gradients_directional(case):
         expect = np.sum(np.conj(w) * lin)
         g = grads[j].cpu().numpy().astype(np.complex128)
         got = np.sum(np.conj(g) * D)
-        scale = np.sqrt(np.sum(np.abs(w) ** 2) * np.sum(np.abs(lin) ** 2))
+        # norm-wise bound on an inner product: tol * ||g|| ||D|| (Cauchy-Schwarz)
+        scale = np.linalg.norm(g) * np.linalg.norm(D)
         assert abs(got - expect) <= tol * scale, (j, got, expect)
 
 
@@ -123,35 +127,42 @@ def _full_size_directional(pl, w_tn, n_dirs=3, seed=3):
         l2[j] = torch.from_numpy(D).to(dev)
         lin = complex(pl.contract(l2).cpu().item())
         expect = np.conj(w) * lin
-        got = np.sum(np.conj(grads[j].cpu().numpy().astype(np.complex128)) * D)
-        print("leaf", j, "adjoint", got, "forward", expect)
-        assert abs(got - expect) <= 1e-5 * abs(w) * abs(lin), (j, got, expect)
+        g = grads[j].cpu().numpy().astype(np.complex128)
+        got = np.sum(np.conj(g) * D)
+        # norm-wise bound on an inner product: 1e-5 ||g|| ||D|| (Cauchy-Schwarz)
+        scale = np.linalg.norm(g) * np.linalg.norm(D.astype(np.complex128))
+        print("leaf", j, "adjoint", got, "forward", expect, "error / scale",
+              abs(got - expect) / scale)
+        assert abs(got - expect) <= 1e-5 * scale, (j, got, expect)
 
 
 def test_full_size_gradient_with_recomputation():
-    """The 30-qubit workload under a workspace cap (80 GiB) that the
-    store-everything backward (about 100 GiB) exceeds: values used inside a
+    """The 30-qubit workload under a workspace cap (28 GiB) that the
+    store-everything backward (about 35 GiB) exceeds: values used inside a
     block are recomputed."""
     from paper_2107_09793_amd import Plan
     _dev()
     wl = workloads.build("sliced", seed=0)
-    pl = Plan.from_network(wl.tn, wl.path, wl.sliced, workspace_limit=80 << 30)
+    full = Plan.from_network(wl.tn, wl.path, wl.sliced, workspace_limit=0, checkpoint="all")
+    assert full.info()["workspace_backward_bytes"] > 28 << 30
+    del full
+    pl = Plan.from_network(wl.tn, wl.path, wl.sliced, workspace_limit=28 << 30)
     info = pl.info()
     assert info["backward_policy"] == 2 and info["cmac_backward_recompute"] > 0
-    assert info["workspace_backward_bytes"] <= 80 << 30
+    assert info["workspace_backward_bytes"] <= 28 << 30
     _full_size_directional(pl, wl.tn)
 
 
 def test_full_size_gradient_with_outer_iterations():
-    """The 30-qubit workload with a 40 GiB cap that the backward must also
+    """The 30-qubit workload with a 20 GiB cap that the backward must also
     fit: part of the slices become outer iterations whose gradients
     accumulate."""
     from paper_2107_09793_amd import Plan
     _dev()
     wl = workloads.build("sliced", seed=0)
-    pl = Plan.from_network(wl.tn, wl.path, wl.sliced, workspace_limit=40 << 30,
+    pl = Plan.from_network(wl.tn, wl.path, wl.sliced, workspace_limit=20 << 30,
                            fit_backward=True)
     info = pl.info()
     assert info["n_outer_bits"] >= 1
-    assert info["workspace_backward_bytes"] <= 40 << 30
+    assert info["workspace_backward_bytes"] <= 20 << 30
     _full_size_directional(pl, wl.tn, seed=4)

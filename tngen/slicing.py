@@ -71,13 +71,18 @@ class TreeSets:
                     flop_sl=flop_sl, n_slices=int(round(2.0 ** nsl_log)))
 
 
-def greedy_slices(ts, n_slice=None, cap_log2=None, max_slices=64):
+def greedy_slices(ts, n_slice=None, cap_log2=None, max_slices=64, initial=()):
     """Pick sliced indices greedily; stop after ``n_slice`` indices, or once the
-    largest per-slice intermediate is at most ``2**cap_log2``."""
+    largest per-slice intermediate is at most ``2**cap_log2``.  ``initial``:
+    indices already sliced (kept first in the returned list)."""
     cand = ~ts.kept
     inter_open = ts.open[ts.n:]
     chosen = np.zeros(len(ts.ids), bool)
+    col = {i: c for c, i in enumerate(ts.ids)}
     out = []
+    for i in initial:
+        chosen[col[i]] = True
+        out.append(i)
     while True:
         ws = ts.w * chosen
         cur = (inter_open * (ts.w - ws)).sum(1)
