@@ -470,6 +470,11 @@ static void schedule(Plan& p) {
   for (const ChainGroup& g : p.chains) {
     const int X = p.steps[g.first].a;
     if (X < p.n_tensors) continue;   // leaf layouts are the caller's
+    // a GEMM result keeps its tile-friendly layout (columns, then rows,
+    // lowest): moving the chain's summed bits lowest would scatter the GEMM
+    // epilogue's stores, and the chain's tile still holds low-stride bits
+    // of its input for contiguous loads
+    if (p.steps[X - p.n_tensors].kind == KIND_GEMM) continue;
     Bits in;
     for (int k = g.first; k <= g.last; ++k)
       for (int32_t b : p.chain_sum_bits[k]) in.push_back(b);
