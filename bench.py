@@ -230,7 +230,7 @@ def cpu_baseline(w, budget_s, max_entries=2 ** 30):
     included."""
     from oracle import tn_oracle
     tn, path, sliced = w.tn, w.path, list(w.sliced)
-    est_rate = 0.3 * zgemm_rate()    # the oracle's rate is below the bare product's
+    est_rate = 0.1 * zgemm_rate()    # the oracle's rate is well below the bare product's
     slice_cost = sum(oracle_step_costs(tn.labels, tn.dims, tn.open, path, sliced)[0])
     n_sl = int(np.prod([tn.dims[e] for e in sliced])) if sliced else 1
     fix = list(sliced)
@@ -255,9 +255,16 @@ def cpu_baseline(w, budget_s, max_entries=2 ** 30):
         fix.append(min(trial)[1])
         costs, big = oracle_step_costs(tn.labels, tn.dims, tn.open, path, fix)
     sub = fix[len(sliced):]
-    radix = [tn.dims[e] for e in fix]
+    t0 = time.perf_counter()
     if not sub:
-        m = int(max(1, min(3, n_sl, budget_s // max(sum(costs) / est_rate, 1e-9))))
+        # whole slices, one at a time, while the next one fits the budget
+        m = 0
+        while m < min(3, n_sl):
+            tn_oracle.contract(tn.tensors, tn.labels, tn.dims, tn.open, path, fix, slice_ids=[m])
+            m += 1
+            el = time.perf_counter() - t0
+            if el * (m + 1) / m > budget_s:
+                break
         ids = list(range(m))
         what = f"{m} whole slice{'s' if m > 1 else ''}"
     else:
@@ -265,8 +272,7 @@ def cpu_baseline(w, budget_s, max_entries=2 ** 30):
         n_sub = int(np.prod([tn.dims[e] for e in sub]))
         what = (f"sub-slice 0 of {n_sub} of slice 0 ({len(sub)} more indices fixed; every "
                 f"step of the path)")
-    t0 = time.perf_counter()
-    tn_oracle.contract(tn.tensors, tn.labels, tn.dims, tn.open, path, fix, slice_ids=ids)
+        tn_oracle.contract(tn.tensors, tn.labels, tn.dims, tn.open, path, fix, slice_ids=ids)
     dt = time.perf_counter() - t0
     cmac = sum(costs) * len(ids)
     rate = cmac / dt
