@@ -137,6 +137,54 @@ def gbs_like(rows, cols, depth, seed, d=4, literal=False):
     return circ
 
 
+def gbs_optical(rows, cols, cycles, seed, d=4, r=0.5):
+    """Random two-dimensional GBS circuit of Alg. 1 with dim = 2 and width =
+    ``cols``: a squeezer S(r) on every mode, then per cycle, for l = 1, 2
+    (stride 1, then ``cols``) and i ascending, a beam splitter BS(theta, phi)
+    on modes (i, i + stride) with theta, phi ~ U(0, 2 pi) -- every pair of
+    the algorithm, row wraps included.  Gates are the truncated Fock-space
+    operators at cutoff ``d`` (``gates.squeezer``, ``gates.beam_splitter``).
+    The paper's GBS-88-m1 is ``gbs_optical(8, 8, 1, seed, d=4, r=0.5)``."""
+    rng = np.random.default_rng([seed, 0])
+    modes = rows * cols
+    llens = [1, cols]
+    circ = Circuit(n=modes, d=d, meta=dict(kind="gbs_optical", rows=rows, cols=cols,
+                                           cycles=cycles, seed=seed, d=d, r=r))
+    S = G.squeezer(r, d)
+    for k in range(modes):
+        circ.add((k,), S, "squeezer")
+    for _ in range(cycles):
+        for stride in llens:
+            for i in range(modes - stride):
+                theta = float(rng.uniform(0.0, 2.0 * np.pi))
+                phi = float(rng.uniform(0.0, 2.0 * np.pi))
+                circ.add((i, i + stride), G.beam_splitter(theta, phi, d), "bs")
+    return circ
+
+
+def gbs_pattern(n, d, r, seed):
+    """A seeded GBS output pattern of typical size: each mode's photon count
+    drawn from a geometric distribution with the mean photon number of a
+    squeezed vacuum, sinh(r)^2, cut at d - 1, then made even in total
+    (``even_total``)."""
+    rng = np.random.default_rng([seed, 1])
+    mean = np.sinh(r) ** 2
+    p = 1.0 / (1.0 + mean)                  # geometric on {0, 1, ...} with that mean
+    x = np.minimum(rng.geometric(p, size=n) - 1, d - 1)
+    return even_total(x)
+
+
+def even_total(pattern):
+    """A GBS output pattern with an even total photon number: squeezed vacua
+    hold even photon numbers only and beam splitters conserve the total, so
+    any pattern with an odd total has amplitude exactly 0.  An odd total is
+    made even by flipping the last entry between 2k and 2k + 1."""
+    x = np.array(pattern, dtype=np.int64)
+    if int(x.sum()) % 2:
+        x[-1] ^= 1
+    return x
+
+
 def ghz(n):
     circ = Circuit(n=n, d=2, meta=dict(kind="ghz", n=n))
     circ.add((0,), G.H, "h")

@@ -51,6 +51,13 @@ CONFIGS = {
     "bosonic": dict(kind="gbs", rows=4, cols=4, depth=6, d=4, n_slice=2, trials=96),
     "gradient": dict(kind="grid", rows=4, cols=5, depth=10, batch=256, trainable=True,
                      n_slice=0, trials=8, refine="time"),
+    # GBS-88-m1 of Sec. 4 (Alg. 1 with squeezers and beam splitters, r = 0.5),
+    # Fock cutoff 4 and 8; output patterns of typical photon numbers
+    # (circuits.gbs_pattern)
+    "gbs": dict(kind="gbs_optical", rows=8, cols=8, cycles=1, d=4, r=0.5, n_slice=0,
+                trials=64, refine="time"),
+    "gbs8": dict(kind="gbs_optical", rows=8, cols=8, cycles=1, d=8, r=0.5, n_slice=0,
+                 trials=64, refine="time"),
 }
 
 # Refined paths are stored (input data, not results): the search takes minutes
@@ -87,14 +94,21 @@ def build(name, seed=0, trials=None, refine=None, use_stored=True, **over):
     if kind == "grid":
         circ = circuits.grid_rqc(cfg["rows"], cfg["cols"], cfg["depth"], seed,
                                  inactive=cfg.get("inactive", ()), trainable=trainable)
+    elif kind == "gbs_optical":
+        circ = circuits.gbs_optical(cfg["rows"], cfg["cols"], cfg["cycles"], seed, d=cfg["d"],
+                                    r=cfg["r"])
     else:
         circ = circuits.gbs_like(cfg["rows"], cfg["cols"], cfg["depth"], seed, d=cfg["d"])
+    levels = min(circ.d, 4) if kind == "gbs_optical" else circ.d
     outcome = batch = None
     if batch_n:
-        batch = circuits.random_bitstrings(circ.n, circ.d, batch_n, seed)
+        batch = circuits.random_bitstrings(circ.n, levels, batch_n, seed)
         tn = network.circuit_network(circ, batch=batch)
+    elif kind == "gbs_optical":
+        outcome = circuits.gbs_pattern(circ.n, circ.d, cfg["r"], seed)
+        tn = network.circuit_network(circ, outcome=outcome)
     else:
-        outcome = circuits.random_bitstrings(circ.n, circ.d, 1, seed)[0]
+        outcome = circuits.random_bitstrings(circ.n, levels, 1, seed)[0]
         tn = network.circuit_network(circ, outcome=outcome)
     tn = network.relabel_compact(tn)
     key = dict(network=network_hash(tn), trials=n_trials, n_slice=n_slice, cap_log2=cap,
