@@ -42,6 +42,10 @@ WORKLOAD_DESC = {
                  "one amplitude, 10 sliced indices (1024 slices)",
     "bosonic": "16-mode 4x4 lattice, Fock cutoff 4, depth 6, Haar two-mode gates, 16 slices",
     "gradient": "20-qubit 4x5 grid, depth 10, batch of 256 outcome strings (forward)",
+    "gbs": "GBS-88-m1: 64-mode 8x8 optical GBS circuit, squeezers r=0.5 + one cycle of "
+           "random beam splitters, Fock cutoff 4, one output pattern",
+    "gbs8": "GBS-88-m1: 64-mode 8x8 optical GBS circuit, squeezers r=0.5 + one cycle of "
+            "random beam splitters, Fock cutoff 8, one output pattern, no slicing",
 }
 
 

@@ -97,3 +97,20 @@ def test_gbs_circuit_and_network():
                                  int(np.base_repr(i, 4).rjust(modes, "0")[q]) for q in
                                  range(modes)) % 2 for i in range(4 ** modes)]))[0]
     assert np.max(np.abs(psi[odd])) < 1e-14
+
+
+def test_three_dimensional_lattice():
+    """Alg. 1 with dim = 3: strides 1, width and width^2, wraps included; the
+    tensor network of a 2x2x2 lattice equals the state vector."""
+    circ = circuits.gbs_optical(2, 2, 1, seed=4, d=4, r=0.5, layers=2)
+    modes = 8
+    pairs = [op.qudits for op in circ.ops if op.name == "bs"]
+    assert pairs == ([(i, i + 1) for i in range(7)] + [(i, i + 2) for i in range(6)] +
+                     [(i, i + 4) for i in range(4)])
+    psi = sv.final_state(circ)
+    for seed in range(2):
+        x = circuits.gbs_pattern(modes, 4, 0.5, seed)
+        tn = network.relabel_compact(network.circuit_network(circ, outcome=x))
+        p = tpath.greedy_path(tn.labels, tn.dims, tn.open)
+        got = complex(tn_oracle.contract(tn.tensors, tn.labels, tn.dims, tn.open, p))
+        assert abs(got - psi[tuple(x)]) <= 1e-12

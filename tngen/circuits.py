@@ -137,19 +137,23 @@ def gbs_like(rows, cols, depth, seed, d=4, literal=False):
     return circ
 
 
-def gbs_optical(rows, cols, cycles, seed, d=4, r=0.5):
-    """Random two-dimensional GBS circuit of Alg. 1 with dim = 2 and width =
-    ``cols``: a squeezer S(r) on every mode, then per cycle, for l = 1, 2
-    (stride 1, then ``cols``) and i ascending, a beam splitter BS(theta, phi)
-    on modes (i, i + stride) with theta, phi ~ U(0, 2 pi) -- every pair of
-    the algorithm, row wraps included.  Gates are the truncated Fock-space
-    operators at cutoff ``d`` (``gates.squeezer``, ``gates.beam_splitter``).
-    The paper's GBS-88-m1 is ``gbs_optical(8, 8, 1, seed, d=4, r=0.5)``."""
+def gbs_optical(rows, cols, cycles, seed, d=4, r=0.5, layers=1):
+    """Random GBS circuit of Alg. 1 on a rows x cols lattice (dim = 2, width =
+    ``cols``) or, with ``layers`` > 1, on a layers x rows x cols lattice
+    (dim = 3, strides 1, cols and rows*cols): a squeezer S(r) on every mode,
+    then per cycle, for each stride in ascending order and i ascending, a
+    beam splitter BS(theta, phi) on modes (i, i + stride) with theta, phi ~
+    U(0, 2 pi) -- every pair of the algorithm, wraps included.  Gates are the
+    truncated Fock-space operators at cutoff ``d`` (``gates.squeezer``,
+    ``gates.beam_splitter``).  The paper's GBS-88-m1 is
+    ``gbs_optical(8, 8, 1, seed, d, r=0.5)`` and its GBS-444-m1 is
+    ``gbs_optical(4, 4, 1, seed, 4, r, layers=4)``."""
     rng = np.random.default_rng([seed, 0])
-    modes = rows * cols
-    llens = [1, cols]
+    modes = layers * rows * cols
+    llens = [1, cols] + ([rows * cols] if layers > 1 else [])
     circ = Circuit(n=modes, d=d, meta=dict(kind="gbs_optical", rows=rows, cols=cols,
-                                           cycles=cycles, seed=seed, d=d, r=r))
+                                           layers=layers, cycles=cycles, seed=seed, d=d,
+                                           r=r))
     S = G.squeezer(r, d)
     for k in range(modes):
         circ.add((k,), S, "squeezer")
