@@ -83,7 +83,14 @@ typedef enum { TN_OUT_SUM = 0, TN_OUT_PER_SLICE = 1 } tn_out_mode;
 #define TN_FLAG_FIT_BACKWARD 256u  /* the resident / outer split also keeps
                                      info.workspace_backward_bytes within
                                      workspace_limit (plans used for gradients)      */
-#define TN_N_GEMM_CONFIGS 8       /* tile configurations per precision              */
+#define TN_N_GEMM_CONFIGS 9       /* tile configurations per precision; the last one
+                                     (8) streams 32-row bands past the whole B block
+                                     of a column tile held in LDS: complex64 steps
+                                     with one batch, at least 2^10 rows and 2^4
+                                     columns, a column tile of min(2^nn, 2^7) columns
+                                     times all k within 2^13 entries and no split k;
+                                     other steps given 8 run with the built-in rule's
+                                     configuration                                  */
 
 typedef struct {
   int32_t precision;          /* tn_precision                                       */

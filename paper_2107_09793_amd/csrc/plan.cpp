@@ -436,22 +436,41 @@ int32_t choose_tile(const Plan& p, int nm, int nn, int nk) {
     }
   }
   if (best >= 0) return best;
+  return rule_tile(nn);
+}
+
+int32_t rule_tile(int nn) {
   if (nn >= 6) return 0;   // 128 x 64
   if (nn == 5) return 1;   // 128 x 32
   return 7;                // 128 x 16
 }
 
+// The stream kernel: one batch, whole 32-row bands, at least one 16-column
+// block, a column tile of min(2^nn, 128) columns whose B block (all k) holds
+// at most 2^13 entries, k tiles of 16 (128 columns) or 32, no split k.
+bool stream_gemm_shape(int nb, int nm, int nn, int nk, int32_t chunks, int32_t precision) {
+  if (precision != PREC_C64 || nb != 0 || nm < 10 || nn < 4 || nn > 17 || chunks > 1)
+    return false;
+  const int ln = std::min(nn, 7), lkt = ln == 7 ? 4 : 5;
+  return nk >= lkt && nk <= 9 && ln + nk <= 13;
+}
+
 // Kernel launches of one execution of a step: split-k runs two kernels; a
 // GEMM step runs one launch per 2^23 output tiles (a dispatch holds fewer
 // than 2^32 work-items of 256-thread workgroups).
-static int32_t step_launches(const StepDesc& S) {
+static int32_t step_launches(const StepDesc& S, int32_t precision) {
   if (S.kind == KIND_SPLITK) return 2;
   if (S.kind == KIND_GEMM && S.splitk_chunks > 1) return 2;   // partial tiles, then their sum
   if (S.kind != KIND_GEMM || S.tile < 0 || S.tile >= kNumGemmConfigs) return 1;
-  static const int lm[kNumGemmConfigs] = {7, 7, 8, 7, 8, 7, 7, 7};   // log2 tile rows
-  static const int ln[kNumGemmConfigs] = {6, 5, 4, 7, 6, 6, 5, 4};   // log2 tile columns
-  const int t = (int)S.bA.size() + std::max(0, (int)S.mA.size() - lm[S.tile]) +
-                std::max(0, (int)S.nB.size() - ln[S.tile]);
+  const int nb = (int)S.bA.size(), nm = (int)S.mA.size(), nn = (int)S.nB.size();
+  int tile = S.tile;
+  if (tile == kGemmStream) {
+    if (stream_gemm_shape(nb, nm, nn, (int)S.kA.size(), S.splitk_chunks, precision)) return 1;
+    tile = rule_tile(nn);
+  }
+  static const int lm[kNumGemmConfigs - 1] = {7, 7, 8, 7, 8, 7, 7, 7};   // log2 tile rows
+  static const int ln[kNumGemmConfigs - 1] = {6, 5, 4, 7, 6, 6, 5, 4};   // log2 tile columns
+  const int t = nb + std::max(0, nm - lm[tile]) + std::max(0, nn - ln[tile]);
   return t > 23 ? 1 << std::min(t - 23, 24) : 1;
 }
 
@@ -818,7 +837,7 @@ static void schedule_pass(Plan& p) {
     double ec = std::ldexp(1.0, (int)p.node_ebits[S.c].size());
     p.bytes_min_exec += mult * 8.0 * (ea + eb + ec);
     p.max_log2_res = std::max(p.max_log2_res, (int32_t)p.node_ebits[S.c].size());
-    (S.phase ? launches1 : launches0) += step_launches(S);
+    (S.phase ? launches1 : launches0) += step_launches(S, p.precision);
   }
   p.n_launches = launches0 + (int32_t)iters * (launches1 + 1) + 1;
   int64_t ctrl = align_up((int64_t)4 << p.resident_bits, 256);
@@ -838,7 +857,7 @@ static void schedule_pass(Plan& p) {
   // launches: one persistent launch replaces its segment's step launches
   for (const Segment& g : p.segments) {
     int32_t saved = 0;
-    for (int q = g.begin; q < g.end; ++q) saved += step_launches(p.steps[p.sched[q]]);
+    for (int q = g.begin; q < g.end; ++q) saved += step_launches(p.steps[p.sched[q]], p.precision);
     int32_t d = saved - 1;
     p.n_launches -= g.phase ? (int32_t)iters * d : d;
   }

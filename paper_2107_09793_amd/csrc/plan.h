@@ -202,8 +202,14 @@ int32_t choose_kind(int nb, int nm, int nn, int nk, uint32_t flags, int32_t* chu
                     int64_t* scratch);
 
 // GEMM tile configuration for a step shape: forced, tune table, or rule.
-constexpr int kNumGemmConfigs = 8;
+// Configuration kGemmStream streams 32-row bands past a B block resident in
+// LDS (few columns and summed values against many rows); a shape it does not
+// take (stream_gemm_shape) runs with the rule's tile configuration instead.
+constexpr int kNumGemmConfigs = 9;
+constexpr int kGemmStream = 8;
 int32_t choose_tile(const Plan& p, int nm, int nn, int nk);
+int32_t rule_tile(int nn);
+bool stream_gemm_shape(int nb, int nm, int nn, int nk, int32_t chunks, int32_t precision);
 
 // Builds the plan; returns empty string on success, else an error message.
 // *unsupported is set when the input is valid but outside what is supported.

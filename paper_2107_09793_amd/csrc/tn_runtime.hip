@@ -20,6 +20,7 @@
 #include "kernels_basic.h"
 #include "kernels_chain.h"
 #include "kernels_gemm.h"
+#include "kernels_gemm_stream.h"
 #include "kernels_persist.h"
 #include "plan.h"
 
@@ -224,8 +225,57 @@ tn_status launch_gemm_cfg(const tnk::StepArgs& a, int32_t precision, hipStream_t
   return TN_OK;
 }
 
+// Stream kernel over 32-row bands (shape checked by stream_gemm_shape).  The
+// k bits go in ascending order of A's strides (k is summed, so any order
+// serves), so that a band's k tile is A's lowest-stride k bits.  One
+// workgroup per CU; the grid is a multiple of 8 workgroups per column tile.
+template <int WN, int LKT>
+void launch_stream_cfg(const tnk::StreamGemmArgs& g, unsigned grid, hipStream_t st) {
+  hipLaunchKernelGGL((tnk::k_gemm_stream_c64<WN, LKT>), dim3(grid), dim3(64 * tnk::kStreamWaves),
+                     0, st, g);
+}
+
+bool launch_gemm_stream(const tnk::StepArgs& a, hipStream_t st) {
+  // in-band offsets of A are held in 32 bits
+  int64_t band_off = 0;
+  for (int j = 0; j < 5; ++j) band_off += (int64_t)1 << a.sA_m[j];
+  for (int j = 0; j < a.nk; ++j) band_off += (int64_t)1 << a.sA_k[j];
+  if (band_off >= (1ll << 32)) return false;
+  tnk::StreamGemmArgs g;
+  memset(&g, 0, sizeof g);
+  g.s = a;
+  int ord[tnk::kMaxBits];
+  for (int j = 0; j < a.nk; ++j) ord[j] = j;
+  std::sort(ord, ord + a.nk, [&](int x, int y) { return a.sA_k[x] < a.sA_k[y]; });
+  for (int j = 0; j < a.nk; ++j) {
+    g.s.sA_k[j] = a.sA_k[ord[j]];
+    g.s.sB_k[j] = a.sB_k[ord[j]];
+  }
+  const int ln = std::min(a.nn, 7), lkt = ln == 7 ? 4 : 5;
+  g.a_mask = tile_mask(5, g.s.sA_m, a.nm, lkt, g.s.sA_k, a.nk);
+  g.lnt = a.nn - ln;
+  g.nbands = 1ull << (a.nm - 5);
+  const uint64_t need = (g.nbands + tnk::kStreamWaves - 1) / tnk::kStreamWaves;
+  uint64_t groups = std::min<uint64_t>(std::max(8, 256 >> g.lnt), need);
+  groups = (groups + 7) / 8 * 8;
+  const unsigned grid = (unsigned)(groups << g.lnt);
+  switch (ln) {
+    case 4: launch_stream_cfg<1, 5>(g, grid, st); break;
+    case 5: launch_stream_cfg<2, 5>(g, grid, st); break;
+    case 6: launch_stream_cfg<4, 5>(g, grid, st); break;
+    default: launch_stream_cfg<8, 4>(g, grid, st); break;
+  }
+  return true;
+}
+
 tn_status launch_gemm(const tnk::StepArgs& a, int32_t precision, int32_t tile, hipStream_t st,
                       int32_t chunks, float2* scratch) {
+  if (tile == tn::kGemmStream) {
+    if (tn::stream_gemm_shape(a.nb, a.nm, a.nn, a.nk, chunks, precision) &&
+        launch_gemm_stream(a, st))
+      return TN_OK;
+    tile = tn::rule_tile(a.nn);
+  }
   switch (tile) {
     case 0: return launch_gemm_cfg<2, 2, 2, 2, 4>(a, precision, st, chunks, scratch);   // 128 x 64
     case 1: return launch_gemm_cfg<4, 1, 1, 2, 4>(a, precision, st, chunks, scratch);   // 128 x 32

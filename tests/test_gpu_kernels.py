@@ -107,9 +107,11 @@ def test_gemm_deterministic_run_to_run(shape):
 
 
 @pytest.mark.parametrize("precision", ["c64", "split_bf16"])
-@pytest.mark.parametrize("cfg", range(8))
+@pytest.mark.parametrize("cfg", range(9))
 def test_every_gemm_tile_config(cfg, precision):
-    """Each compiled tile configuration, forced on a full and a partial tile shape."""
+    """Each compiled tile configuration, forced on a full and a partial tile shape
+    (the stream configuration, 8, does not take these shapes and runs them with
+    the rule's configuration)."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2107_09793_amd import Plan
@@ -126,3 +128,79 @@ def test_every_gemm_tile_config(cfg, precision):
                                  labels, dims, open_ids, [(0, 1)])
         err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
         assert err <= (1e-5 if precision == "c64" else 1e-4), (shape, err)
+
+
+STREAM_CASES = [
+    # (nb, nm, nn, nk, d4): column blocks of 16, 32, 64, 128; several bands per
+    # wave; one k tile per band; column tiles; dim-4 rows; K up to 512
+    (0, 17, 7, 6, 0),
+    (0, 12, 4, 9, 0),
+    (0, 12, 5, 8, 0),
+    (0, 13, 6, 5, 0),
+    (0, 11, 9, 6, 0),
+    (0, 10, 7, 4, 1),
+    (0, 10, 5, 5, 0),   # fewer bands than waves
+    (1, 12, 7, 6, 0),   # batch bit: runs with the rule's configuration
+]
+
+
+@pytest.mark.parametrize("precision", ["c64", "split_bf16"])
+@pytest.mark.parametrize("shape", STREAM_CASES, ids=lambda c: "b%dm%dn%dk%dd%d" % c)
+def test_stream_gemm(shape, precision):
+    """The stream configuration (B block resident in LDS, 32-row bands) forced
+    on the shapes it takes, against the oracle; split-BF16 and the batch
+    shape run with the rule's configuration."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2107_09793_amd import Plan
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng([8, *shape])
+    tensors, labels, dims, open_ids = _case(rng, *shape)
+    pl = Plan(labels, dims, open_ids, [(0, 1)], precision=precision, gemm_config=8)
+    st = pl.step(0)
+    assert st["kind_name"] == "gemm" and st["tile"] == 8 and st["chunks"] <= 1
+    leaves = [torch.from_numpy(t.astype(np.complex64)).to(dev) for t in tensors]
+    got = pl.contract(leaves).cpu().numpy()
+    x = pl.contract(leaves).cpu().numpy()
+    assert np.array_equal(got, x)
+    ref = tn_oracle.contract([t.astype(np.complex64).astype(np.complex128) for t in tensors],
+                             labels, dims, open_ids, [(0, 1)])
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print("stream", shape, precision, err)
+    assert err <= (1e-5 if precision == "c64" else 1e-4), err
+
+
+@pytest.mark.parametrize("shape", [(0, 12, 6, 6, 0), (0, 11, 8, 5, 0)])
+def test_stream_gemm_adjoint(shape):
+    """Leaf gradients of a single product C = A B with the stream configuration
+    forced: the adjoint step for A, grad_A = grad_C B^H, is a stream-shaped
+    GEMM with B conjugated that adds into the gradient buffer.  Reference: the
+    same product in complex128."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2107_09793_amd import Plan
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng([9, *shape])
+    tensors, labels, dims, open_ids = _case(rng, *shape)
+    pl = Plan(labels, dims, open_ids, [(0, 1)], gemm_config=8)
+    leaves = [torch.from_numpy(t.astype(np.complex64)).to(dev) for t in tensors]
+    out = pl.contract(leaves)
+    w = (rng.standard_normal(out.shape) + 1j * rng.standard_normal(out.shape)).astype(np.complex64)
+    # backward adds into the gradient buffers: start them non-zero
+    g0 = [(rng.standard_normal(t.shape) + 1j * rng.standard_normal(t.shape)).astype(np.complex64)
+          for t in tensors]
+    grads = [torch.from_numpy(g).to(dev) for g in g0]
+    pl.backward(leaves, torch.from_numpy(w).to(dev), grads)
+    a, b = [t.astype(np.complex64).astype(np.complex128) for t in tensors]
+    la, lb = labels
+    sym = {i: chr(97 + n) for n, i in enumerate(sorted(set(la) | set(lb)))}
+    sa = "".join(sym[i] for i in la)
+    sb = "".join(sym[i] for i in lb)
+    so = "".join(sym[i] for i in open_ids)
+    wd = w.astype(np.complex128)
+    ga = np.einsum(f"{so},{sb}->{sa}", wd, np.conj(b))
+    gb = np.einsum(f"{so},{sa}->{sb}", wd, np.conj(a))
+    for got, ref, init in ((grads[0], ga, g0[0]), (grads[1], gb, g0[1])):
+        got = got.cpu().numpy().astype(np.complex128) - init
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        assert err <= 1e-5, err
