@@ -85,11 +85,13 @@ typedef enum { TN_OUT_SUM = 0, TN_OUT_PER_SLICE = 1 } tn_out_mode;
                                      workspace_limit (plans used for gradients)      */
 #define TN_N_GEMM_CONFIGS 9       /* tile configurations per precision; the last one
                                      (8) streams 32-row bands past the whole B block
-                                     of a column tile held in LDS: complex64 steps
-                                     with one batch, at least 2^10 rows and 2^4
-                                     columns, a column tile of min(2^nn, 2^7) columns
-                                     times all k within 2^13 entries and no split k;
-                                     other steps given 8 run with the built-in rule's
+                                     of a column tile held in LDS: steps with one
+                                     batch, at least 2^10 rows and 2^4 columns, no
+                                     split k and a column tile whose B block (all k)
+                                     fits 64 KiB (complex64: 2^min(nn,7) columns and
+                                     at most 2^13 entries; split-BF16: 2^min(nn,6)
+                                     columns and at most 2^12 entries); other steps
+                                     given 8 run with the built-in rule's
                                      configuration                                  */
 
 typedef struct {

@@ -446,13 +446,26 @@ int32_t rule_tile(int nn) {
 }
 
 // The stream kernel: one batch, whole 32-row bands, at least one 16-column
-// block, a column tile of min(2^nn, 128) columns whose B block (all k) holds
-// at most 2^13 entries, k tiles of 16 (128 columns) or 32, no split k.
+// block, no split k, and a column tile of 2^ln columns whose B block (all k)
+// fits the 64 KiB buffer: 8 bytes per complex entry in complex64 (ln <= 7,
+// k tiles of 16 at 128 columns, else 32), 16 in split-BF16 (the embedded hi
+// and lo operands; ln <= min(6, 12 - nk), k tiles of 32).
+void stream_gemm_tile(int nn, int nk, int32_t precision, int* ln, int* lkt) {
+  if (precision == PREC_SPLIT_BF16) {
+    *ln = std::min(std::min(nn, 6), 12 - nk);
+    *lkt = 5;
+  } else {
+    *ln = std::min(nn, 7);
+    *lkt = *ln == 7 ? 4 : 5;
+  }
+}
+
 bool stream_gemm_shape(int nb, int nm, int nn, int nk, int32_t chunks, int32_t precision) {
-  if (precision != PREC_C64 || nb != 0 || nm < 10 || nn < 4 || nn > 17 || chunks > 1)
-    return false;
-  const int ln = std::min(nn, 7), lkt = ln == 7 ? 4 : 5;
-  return nk >= lkt && nk <= 9 && ln + nk <= 13;
+  if (nb != 0 || nm < 10 || nn < 4 || chunks > 1 || nk > 9) return false;
+  int ln, lkt;
+  stream_gemm_tile(nn, nk, precision, &ln, &lkt);
+  if (ln < 4 || nn - ln > 10 || nk < lkt) return false;
+  return ln + nk <= (precision == PREC_SPLIT_BF16 ? 12 : 13);
 }
 
 // Kernel launches of one execution of a step: split-k runs two kernels; a

@@ -210,6 +210,8 @@ constexpr int kGemmStream = 8;
 int32_t choose_tile(const Plan& p, int nm, int nn, int nk);
 int32_t rule_tile(int nn);
 bool stream_gemm_shape(int nb, int nm, int nn, int nk, int32_t chunks, int32_t precision);
+// Column tile (log2 columns) and k tile (log2 complex k) of the stream kernel.
+void stream_gemm_tile(int nn, int nk, int32_t precision, int* ln, int* lkt);
 
 // Builds the plan; returns empty string on success, else an error message.
 // *unsupported is set when the input is valid but outside what is supported.

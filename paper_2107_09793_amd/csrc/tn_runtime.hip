@@ -227,15 +227,15 @@ tn_status launch_gemm_cfg(const tnk::StepArgs& a, int32_t precision, hipStream_t
 
 // Stream kernel over 32-row bands (shape checked by stream_gemm_shape).  The
 // k bits go in ascending order of A's strides (k is summed, so any order
-// serves), so that a band's k tile is A's lowest-stride k bits.  One
-// workgroup per CU; the grid is a multiple of 8 workgroups per column tile.
-template <int WN, int LKT>
+// serves), so that a band's k tile is A's lowest-stride k bits.  About one
+// workgroup per CU; a power of two (at least 8) of workgroups per column tile.
+template <template <int> class P, int WN, int LKT, int DEPTH>
 void launch_stream_cfg(const tnk::StreamGemmArgs& g, unsigned grid, hipStream_t st) {
-  hipLaunchKernelGGL((tnk::k_gemm_stream_c64<WN, LKT>), dim3(grid), dim3(64 * tnk::kStreamWaves),
-                     0, st, g);
+  hipLaunchKernelGGL((tnk::k_gemm_stream<P, WN, LKT, DEPTH>), dim3(grid),
+                     dim3(64 * tnk::kStreamWaves), 0, st, g);
 }
 
-bool launch_gemm_stream(const tnk::StepArgs& a, hipStream_t st) {
+bool launch_gemm_stream(const tnk::StepArgs& a, int32_t precision, hipStream_t st) {
   // in-band offsets of A are held in 32 bits
   int64_t band_off = 0;
   for (int j = 0; j < 5; ++j) band_off += (int64_t)1 << a.sA_m[j];
@@ -251,19 +251,30 @@ bool launch_gemm_stream(const tnk::StepArgs& a, hipStream_t st) {
     g.s.sA_k[j] = a.sA_k[ord[j]];
     g.s.sB_k[j] = a.sB_k[ord[j]];
   }
-  const int ln = std::min(a.nn, 7), lkt = ln == 7 ? 4 : 5;
+  int ln, lkt;
+  tn::stream_gemm_tile(a.nn, a.nk, precision, &ln, &lkt);
   g.a_mask = tile_mask(5, g.s.sA_m, a.nm, lkt, g.s.sA_k, a.nk);
   g.lnt = a.nn - ln;
   g.nbands = 1ull << (a.nm - 5);
-  const uint64_t need = (g.nbands + tnk::kStreamWaves - 1) / tnk::kStreamWaves;
-  uint64_t groups = std::min<uint64_t>(std::max(8, 256 >> g.lnt), need);
-  groups = (groups + 7) / 8 * 8;
-  const unsigned grid = (unsigned)(groups << g.lnt);
+  // 2^lgroups band groups of 8 waves per column tile (at least 8, one per
+  // XCD), about one workgroup per CU in all, never more than the bands need
+  int lg = 3;
+  while (lg < 8 - g.lnt && (1ull << (lg + 1 + 3)) <= g.nbands) ++lg;
+  g.lgroups = lg;
+  const unsigned grid = 1u << (lg + g.lnt);
+  if (precision == tn::PREC_SPLIT_BF16) {
+    switch (ln) {
+      case 4: launch_stream_cfg<tnk::StreamSB16, 1, 5, 2>(g, grid, st); break;
+      case 5: launch_stream_cfg<tnk::StreamSB16, 2, 5, 2>(g, grid, st); break;
+      default: launch_stream_cfg<tnk::StreamSB16, 4, 5, 2>(g, grid, st); break;
+    }
+    return true;
+  }
   switch (ln) {
-    case 4: launch_stream_cfg<1, 5>(g, grid, st); break;
-    case 5: launch_stream_cfg<2, 5>(g, grid, st); break;
-    case 6: launch_stream_cfg<4, 5>(g, grid, st); break;
-    default: launch_stream_cfg<8, 4>(g, grid, st); break;
+    case 4: launch_stream_cfg<tnk::StreamC64, 1, 5, 2>(g, grid, st); break;
+    case 5: launch_stream_cfg<tnk::StreamC64, 2, 5, 2>(g, grid, st); break;
+    case 6: launch_stream_cfg<tnk::StreamC64, 4, 5, 2>(g, grid, st); break;
+    default: launch_stream_cfg<tnk::StreamC64, 8, 4, 1>(g, grid, st); break;
   }
   return true;
 }
@@ -272,7 +283,7 @@ tn_status launch_gemm(const tnk::StepArgs& a, int32_t precision, int32_t tile, h
                       int32_t chunks, float2* scratch) {
   if (tile == tn::kGemmStream) {
     if (tn::stream_gemm_shape(a.nb, a.nm, a.nn, a.nk, chunks, precision) &&
-        launch_gemm_stream(a, st))
+        launch_gemm_stream(a, precision, st))
       return TN_OK;
     tile = tn::rule_tile(a.nn);
   }

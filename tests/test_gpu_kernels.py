@@ -147,9 +147,11 @@ STREAM_CASES = [
 @pytest.mark.parametrize("precision", ["c64", "split_bf16"])
 @pytest.mark.parametrize("shape", STREAM_CASES, ids=lambda c: "b%dm%dn%dk%dd%d" % c)
 def test_stream_gemm(shape, precision):
-    """The stream configuration (B block resident in LDS, 32-row bands) forced
-    on the shapes it takes, against the oracle; split-BF16 and the batch
-    shape run with the rule's configuration."""
+    """The stream configuration (B block resident in LDS, 32-row bands) forced,
+    against the oracle: complex64 takes every shape but the batch one;
+    split-BF16 (B blocks of at most 2^12 entries, k tiles of 32) takes
+    m17n7k6 (two column tiles), m12n5k8 (two), m13n6k5, m11n9k6 (eight) and
+    m10n5k5; the others run with the rule's configuration."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2107_09793_amd import Plan
@@ -168,10 +170,13 @@ def test_stream_gemm(shape, precision):
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
     print("stream", shape, precision, err)
     assert err <= (1e-5 if precision == "c64" else 1e-4), err
+    if precision == "split_bf16":
+        assert err > 1e-9   # really ran in reduced precision
 
 
+@pytest.mark.parametrize("precision", ["c64", "split_bf16"])
 @pytest.mark.parametrize("shape", [(0, 12, 6, 6, 0), (0, 11, 8, 5, 0)])
-def test_stream_gemm_adjoint(shape):
+def test_stream_gemm_adjoint(shape, precision):
     """Leaf gradients of a single product C = A B with the stream configuration
     forced: the adjoint step for A, grad_A = grad_C B^H, is a stream-shaped
     GEMM with B conjugated that adds into the gradient buffer.  Reference: the
@@ -182,7 +187,7 @@ def test_stream_gemm_adjoint(shape):
     dev = torch.device("cuda:0")
     rng = np.random.default_rng([9, *shape])
     tensors, labels, dims, open_ids = _case(rng, *shape)
-    pl = Plan(labels, dims, open_ids, [(0, 1)], gemm_config=8)
+    pl = Plan(labels, dims, open_ids, [(0, 1)], gemm_config=8, precision=precision)
     leaves = [torch.from_numpy(t.astype(np.complex64)).to(dev) for t in tensors]
     out = pl.contract(leaves)
     w = (rng.standard_normal(out.shape) + 1j * rng.standard_normal(out.shape)).astype(np.complex64)
@@ -203,4 +208,4 @@ def test_stream_gemm_adjoint(shape):
     for got, ref, init in ((grads[0], ga, g0[0]), (grads[1], gb, g0[1])):
         got = got.cpu().numpy().astype(np.complex128) - init
         err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
-        assert err <= 1e-5, err
+        assert err <= (1e-5 if precision == "c64" else 1e-4), err
