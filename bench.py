@@ -137,7 +137,9 @@ def roofline(unit, avg_s, precision):
 
 
 KERNEL_SOURCES = {
-    "gemm": ("paper_2107_09793_amd/csrc/kernels_gemm.h", "paper_2107_09793_amd/csrc/kernels_common.h"),
+    "gemm": ("paper_2107_09793_amd/csrc/kernels_gemm.h",
+             "paper_2107_09793_amd/csrc/kernels_gemm_stream.h",
+             "paper_2107_09793_amd/csrc/kernels_common.h"),
     "stream": ("paper_2107_09793_amd/csrc/kernels_basic.h", "paper_2107_09793_amd/csrc/kernels_common.h"),
     "chain": ("paper_2107_09793_amd/csrc/kernels_chain.h", "paper_2107_09793_amd/csrc/kernels_common.h"),
 }

@@ -29,7 +29,7 @@ N_CONFIGS = 9
 CONFIG_NAMES = {0: "128x64 k16", 1: "128x32 k16", 2: "256x16 k16", 3: "128x128 k16",
                 4: "256x64 k16", 5: "128x64 k32 (c64) / k16 (split)",
                 6: "128x32 k8 (c64) / k16 (split)", 7: "128x16 k16",
-                8: "stream: 32-row bands past a resident B block (c64; else the rule's)"}
+                8: "stream: 32-row bands past a resident B block"}
 PREC_ID = {"c64": 0, "split_bf16": 1}
 
 
