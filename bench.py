@@ -60,7 +60,8 @@ def launch_units(plan, steps):
         if s["chain"] >= 0:
             continue
         units[k] = dict(kind=s["kind_name"], cmac=s["cmac"], bytes=s["bytes"], phase=s["phase"],
-                        steps=[k], shape=dict(nb=s["nb"], nm=s["nm"], nn=s["nn"], nk=s["nk"]))
+                        steps=[k], shape=dict(nb=s["nb"], nm=s["nm"], nn=s["nn"], nk=s["nk"]),
+                        tile_run=s["tile_run"])
     for ch in chains:
         mem = [steps[d["step"]] for d in ch["st"]]
         f, l = mem[0], mem[-1]
@@ -101,16 +102,25 @@ def dominant_unit(plan, leaves, info, units, torch):
 
 def roofline(unit, avg_s, precision):
     """The unit's bound is the larger of its HBM time (algorithmic bytes at
-    8 TB/s) and its compute time (MFMA for GEMM steps at the precision's
-    peak, counting the three products of split-BF16; for chain steps MFMA
-    at the precision's peak or FP32 vector FMA, as the chain runs them;
-    FP32 vector FMA for the others); achieved is measured in that bound's
-    unit against the peak of the units doing most of the work."""
+    8 TB/s) and its compute time (the MFMA work its kernel executes at the
+    precision's peak: 8 real flops per complex multiply-add in the real
+    embedding, 6 with three real products per complex product (GEMM tile
+    configuration 9), three BF16 products of 8 in split-BF16; for chain steps
+    MFMA at the precision's peak or FP32 vector FMA, as the chain runs them;
+    FP32 vector FMA for the others).  Achieved is measured in that bound's
+    unit: algorithmic bytes, or algorithmic flops (8 per complex multiply-add,
+    the complex GEMM's 2 M N K complex flops) against the peak of the units
+    doing most of the work; a GEMM also reports the executed MFMA flops per
+    complex multiply-add and the matrix cores' use (executed flops / peak)."""
     kind = unit["kind"]
+    extra = {}
     if kind == "gemm":
-        flops = 8.0 * unit["cmac"] * (3.0 if precision == "split_bf16" else 1.0)
+        flops = 8.0 * unit["cmac"]
+        per = 24.0 if precision == "split_bf16" else (6.0 if unit.get("tile_run") == 9 else 8.0)
         peak, cbound = PEAKS["mfma_" + precision], "mfma"
-        t_cmp = flops / (peak * 1e12)
+        t_cmp = per * unit["cmac"] / (peak * 1e12)
+        extra = dict(executed_flops_per_cmac=per,
+                     mfma_util=per * unit["cmac"] / avg_s / 1e12 / peak)
     elif kind == "chain":
         # chain steps run on the matrix cores (FP32, or three BF16 products
         # in split-BF16 plans) or on the FP32 vector units
@@ -131,9 +141,9 @@ def roofline(unit, avg_s, precision):
     if t_mem >= t_cmp:
         ach = unit["bytes"] / avg_s / 1e9
         return dict(bound="hbm", achieved=ach, peak=PEAKS["hbm"], unit="GB/s",
-                    frac=ach / PEAKS["hbm"])
+                    frac=ach / PEAKS["hbm"], **extra)
     ach = flops / avg_s / 1e12
-    return dict(bound=cbound, achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak)
+    return dict(bound=cbound, achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak, **extra)
 
 
 KERNEL_SOURCES = {

@@ -83,16 +83,20 @@ typedef enum { TN_OUT_SUM = 0, TN_OUT_PER_SLICE = 1 } tn_out_mode;
 #define TN_FLAG_FIT_BACKWARD 256u  /* the resident / outer split also keeps
                                      info.workspace_backward_bytes within
                                      workspace_limit (plans used for gradients)      */
-#define TN_N_GEMM_CONFIGS 9       /* tile configurations per precision; the last one
-                                     (8) streams 32-row bands past the whole B block
-                                     of a column tile held in LDS: steps with one
-                                     batch, at least 2^10 rows and 2^4 columns, no
-                                     split k and a column tile whose B block (all k)
-                                     fits 64 KiB (complex64: 2^min(nn,7) columns and
-                                     at most 2^13 entries; split-BF16: 2^min(nn,6)
-                                     columns and at most 2^12 entries); other steps
-                                     given 8 run with the built-in rule's
-                                     configuration                                  */
+#define TN_N_GEMM_CONFIGS 10      /* tile configurations per precision.  8 streams
+                                     32-row bands past the whole B block of a column
+                                     tile held in LDS: steps with one batch, at least
+                                     2^10 rows and 2^4 columns, no split k and a
+                                     column tile whose B block (all k) fits 64 KiB
+                                     (complex64: 2^min(nn,7) columns and at most
+                                     2^13 entries; split-BF16: 2^min(nn,6) columns
+                                     and at most 2^12 entries).  9 is 8 with three
+                                     real products per complex product (complex64,
+                                     5 <= nk <= 7, column tiles of
+                                     2^min(nn, 6, 12 - nk) >= 32 columns).  A step
+                                     given 9 that it does not take runs as 8, and
+                                     one given 8 that 8 does not take runs with the
+                                     built-in rule's configuration                  */
 
 typedef struct {
   int32_t precision;          /* tn_precision                                       */
@@ -196,6 +200,10 @@ typedef struct {
   int32_t chunks;             /* split-k kernels and GEMM steps split over k: chunks
                                  of the summed bits, added up in a fixed order (1:
                                  no split)                                          */
+  int32_t tile_run;           /* the GEMM tile configuration that runs: tile, or
+                                 where a stream configuration (8, 9) does not take
+                                 the step's shape the one it falls back to (see
+                                 TN_N_GEMM_CONFIGS); -1 for other kinds           */
 } tn_step_info;
 
 /* One fused chain as planned (tests).  A chain runs steps first..last (path

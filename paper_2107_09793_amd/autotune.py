@@ -25,11 +25,12 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(HERE))
 
-N_CONFIGS = 9
+N_CONFIGS = 10
 CONFIG_NAMES = {0: "128x64 k16", 1: "128x32 k16", 2: "256x16 k16", 3: "128x128 k16",
                 4: "256x64 k16", 5: "128x64 k32 (c64) / k16 (split)",
                 6: "128x32 k8 (c64) / k16 (split)", 7: "128x16 k16",
-                8: "stream: 32-row bands past a resident B block"}
+                8: "stream: 32-row bands past a resident B block",
+                9: "stream, three real products per complex product (c64; else as 8)"}
 PREC_ID = {"c64": 0, "split_bf16": 1}
 
 

@@ -71,7 +71,7 @@ class StepInfo(ctypes.Structure):
         [(n, I8x48) for n in ("sA_b", "sB_b", "sC_b", "sA_m", "sC_m", "sB_n", "sC_n",
                               "sA_k", "sB_k")] + \
         [("c_offset", ctypes.c_int64), ("c_bytes", ctypes.c_int64),
-         ("chain", ctypes.c_int32), ("chunks", ctypes.c_int32)]
+         ("chain", ctypes.c_int32), ("chunks", ctypes.c_int32), ("tile_run", ctypes.c_int32)]
 
 
 class ChainStepInfo(ctypes.Structure):

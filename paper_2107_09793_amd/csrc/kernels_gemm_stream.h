@@ -48,6 +48,38 @@ struct StreamGemmArgs {
   uint64_t nbands;   // 32-row bands: 2^(nm - 5)
 };
 
+// Result stores of the real-embedded layout (both precisions): lane holds
+// real column l31 of each 32 x 32 block j (Re, par 0, or Im, par 1, of
+// complex column 16 j + l31 / 2), rows 8 (q / 4) + 4 half + q % 4 of
+// accumulator entry q.  C += result when accumulating.
+template <int WN>
+__device__ __forceinline__ void store_embedded(float2* C2, int64_t cbase, const int64_t* t_cn,
+                                               const int64_t* t_cm, int lane, int accumulate,
+                                               floatx16 (&acc)[WN]) {
+  const int half = lane >> 5, par = lane & 1, l31 = lane & 31;
+  float* C = reinterpret_cast<float*>(C2);
+#pragma unroll
+  for (int j = 0; j < WN; ++j) {
+    const int64_t on = cbase + t_cn[j * 16 + (l31 >> 1)];
+    auto at = [&](int q) -> float& {
+      return C[2 * (on + t_cm[8 * (q >> 2) + 4 * half + (q & 3)]) + par];
+    };
+    if (accumulate) {
+#pragma unroll
+      for (int q0 = 0; q0 < 16; q0 += 4) {
+        float old[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) old[q] = at(q0 + q);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) at(q0 + q) = old[q] + acc[j][q0 + q];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) at(q) = acc[j][q];
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // complex64 operands.  A k tile in LDS: the Re plane (KT x 32 floats, the 32
 // rows of one k consecutive and XOR-swizzled by k so that staging writes of
@@ -58,6 +90,13 @@ template <int KT>
 struct StreamC64 {
   static constexpr int kIm = KT * 32 + 32;
   static constexpr int kWaveBytes = (kIm + KT * 32) * 4;
+  template <int WN>
+  static constexpr int kAcc = WN;   // one 32 x 32 real block per 16 columns
+  template <int WN>
+  __device__ static void store(float2* C, int64_t cbase, const int64_t* t_cn, const int64_t* t_cm,
+                               int lane, int accumulate, floatx16 (&acc)[WN]) {
+    store_embedded<WN>(C, cbase, t_cn, t_cm, lane, accumulate, acc);
+  }
 
   __device__ static int a_pos(int ki, int mi) { return ki * 32 + (mi ^ ((ki << 2) & 31)); }
   __device__ static void put_a(char* sa, int pos, float2 v) {
@@ -121,6 +160,13 @@ struct StreamSB16 {
   static constexpr int kWaveBytes = 2 * kPlane;
   static constexpr int kSwzShift = KT == 32 ? 1 : 2;   // rows sharing banks: 256 B / row bytes
   static_assert(KT == 16 || KT == 32, "split-BF16 stream tiles walk k by 16 or 32");
+  template <int WN>
+  static constexpr int kAcc = WN;
+  template <int WN>
+  __device__ static void store(float2* C, int64_t cbase, const int64_t* t_cn, const int64_t* t_cm,
+                               int lane, int accumulate, floatx16 (&acc)[WN]) {
+    store_embedded<WN>(C, cbase, t_cn, t_cm, lane, accumulate, acc);
+  }
 
   __device__ static int chunk(int row, int q) { return q ^ ((row >> kSwzShift) & (kChunks - 1)); }
   __device__ static int a_pos(int ki, int mi) {
@@ -168,7 +214,87 @@ struct StreamSB16 {
 };
 
 // ---------------------------------------------------------------------------
-// The stream kernel.  P: operand policy (StreamC64 / StreamSB16); WN: 16-column
+// complex64 with three real products per complex product (Gauss):
+// T1 = Re A Re B, T2 = Im A Im B, T3 = (Re A + Im A)(Re B + Im B) summed over
+// k, then Re C = T1 - T2 and Im C = T3 - T1 - T2: three v_mfma_f32_32x32x2f32
+// per two complex k and 32 complex columns, where the real embedding takes
+// four.  The MFMA columns are complex columns (blocks of 32), so WN (16-column
+// units) is even and block b holds accumulators 3 b .. 3 b + 2.  A k tile in
+// LDS: the Re and Im planes, each [k / 2][row][k % 2] (the two k of one MFMA
+// side by side, so the two half-waves read the even and the odd banks); the
+// sum Re A + Im A is formed on reading.  B: the planes Re B, Im B and
+// Re B + Im B, each [k / 2][column][k % 2].
+template <int KT>
+struct StreamC64G {
+  static constexpr int kPlane = KT * 32;   // floats of one A plane
+  static constexpr int kWaveBytes = 2 * kPlane * 4;
+  template <int WN>
+  static constexpr int kAcc = 3 * (WN / 2);
+
+  __device__ static int a_pos(int ki, int mi) { return ((ki >> 1) * 32 + mi) * 2 + (ki & 1); }
+  __device__ static void put_a(char* sa, int pos, float2 v) {
+    float* f = reinterpret_cast<float*>(sa);
+    f[pos] = v.x;
+    f[kPlane + pos] = v.y;
+  }
+  template <int NT>
+  __device__ static void put_b(char* sb, int k, int n, float2 v, int K) {
+    float* f = reinterpret_cast<float*>(sb);
+    const int plane = K * NT;
+    const int pos = ((k >> 1) * NT + n) * 2 + (k & 1);
+    f[pos] = v.x;
+    f[plane + pos] = v.y;
+    f[2 * plane + pos] = v.x + v.y;
+  }
+  template <int WN, int NT>
+  __device__ static void tile(const char* sa, const char* sb, int kt, int lane, int K,
+                              floatx16 (&acc)[kAcc<WN>]) {
+    constexpr int NB = WN / 2;
+    const int half = lane >> 5, l31 = lane & 31;
+    const int plane = K * NT;
+    const float* ar = reinterpret_cast<const float*>(sa) + l31 * 2 + half;
+    const float* bp = reinterpret_cast<const float*>(sb) + (kt * (KT / 2) * NT + l31) * 2 + half;
+#pragma unroll 2
+    for (int k2 = 0; k2 < KT / 2; ++k2) {
+      const float a_r = ar[k2 * 64], a_i = ar[kPlane + k2 * 64];
+      const float a_s = a_r + a_i;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const float* bb = bp + (k2 * NT + b * 32) * 2;
+        const float b_r = bb[0], b_i = bb[plane], b_s = bb[2 * plane];
+        acc[3 * b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_r, b_r, acc[3 * b], 0, 0, 0);
+        acc[3 * b + 1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_i, b_i, acc[3 * b + 1], 0, 0, 0);
+        acc[3 * b + 2] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_s, b_s, acc[3 * b + 2], 0, 0, 0);
+      }
+    }
+  }
+  // lane holds complex column 32 b + l31 of block b, rows 8 (q / 4) + 4 half
+  // + q % 4 of entry q of its three accumulators
+  template <int WN>
+  __device__ static void store(float2* C, int64_t cbase, const int64_t* t_cn, const int64_t* t_cm,
+                               int lane, int accumulate, floatx16 (&acc)[kAcc<WN>]) {
+    constexpr int NB = WN / 2;
+    const int half = lane >> 5, l31 = lane & 31;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int64_t on = cbase + t_cn[b * 32 + l31];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const float t1 = acc[3 * b][q], t2 = acc[3 * b + 1][q], t3 = acc[3 * b + 2][q];
+        float2 v = make_float2(t1 - t2, t3 - t1 - t2);
+        float2* cp = C + on + t_cm[8 * (q >> 2) + 4 * half + (q & 3)];
+        if (accumulate) {
+          const float2 o = *cp;
+          v = make_float2(o.x + v.x, o.y + v.y);
+        }
+        *cp = v;
+      }
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// The stream kernel.  P: operand policy (StreamC64, StreamC64G, StreamSB16); WN: 16-column
 // blocks per column tile; LKT: log2 complex k per k tile; DEPTH: k tiles in
 // flight per wave besides the one in LDS (1 or 2).
 template <template <int> class P, int WN, int LKT, int DEPTH>
@@ -234,7 +360,6 @@ __global__ void __launch_bounds__(64 * kStreamWaves) k_gemm_stream(StreamGemmArg
   const uint64_t nunits = nbw * (uint64_t)nkt;
   char* sa = &sA[wave][0];
   const float asign = p.conjA ? -1.f : 1.f;
-  const int half = lane >> 5, par = lane & 1, l31 = lane & 31;
 
   struct Walk {   // position in the wave's units and the base offset there
     int kt;
@@ -279,10 +404,10 @@ __global__ void __launch_bounds__(64 * kStreamWaves) k_gemm_stream(StreamGemmArg
   if (ul < nunits) load(rx);
   if (DEPTH == 2 && ul < nunits) load(ry);
 
-  floatx16 acc[WN];
+  constexpr int NACC = Pol::template kAcc<WN>;
+  floatx16 acc[NACC];
 #pragma unroll
-  for (int j = 0; j < WN; ++j) acc[j] = floatx16{};
-  float* C = reinterpret_cast<float*>(p.C);
+  for (int j = 0; j < NACC; ++j) acc[j] = floatx16{};
   // One unit: the matrix-core work on the staged tile, then the next tile
   // (held in slot r) into LDS and slot r refilled with the unit DEPTH + 1
   // ahead, then -- at the end of a band -- the result stores.  Staging before
@@ -294,29 +419,9 @@ __global__ void __launch_bounds__(64 * kStreamWaves) k_gemm_stream(StreamGemmArg
     if (more) stage(r);
     if (ul < nunits) load(r);
     if (wc.kt == nkt - 1) {
-      // the band's result: lane holds real column l31 of each 32 x 32 block,
-      // rows 8 (r / 4) + 4 half + r % 4 of accumulator entry r
+      Pol::template store<WN>(p.C, wc.base, t_cn, t_cm, lane, p.accumulate, acc);
 #pragma unroll
-      for (int j = 0; j < WN; ++j) {
-        const int64_t on = wc.base + t_cn[j * 16 + (l31 >> 1)];
-        auto at = [&](int q) -> float& {
-          return C[2 * (on + t_cm[8 * (q >> 2) + 4 * half + (q & 3)]) + par];
-        };
-        if (p.accumulate) {
-#pragma unroll
-          for (int q0 = 0; q0 < 16; q0 += 4) {
-            float old[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) old[q] = at(q0 + q);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) at(q0 + q) = old[q] + acc[j][q0 + q];
-          }
-        } else {
-#pragma unroll
-          for (int q = 0; q < 16; ++q) at(q) = acc[j][q];
-        }
-        acc[j] = floatx16{};
-      }
+      for (int q = 0; q < NACC; ++q) acc[q] = floatx16{};
     }
     advance(wc, S.Cm());
     ++uc;

@@ -468,6 +468,27 @@ bool stream_gemm_shape(int nb, int nm, int nn, int nk, int32_t chunks, int32_t p
   return ln + nk <= (precision == PREC_SPLIT_BF16 ? 12 : 13);
 }
 
+// The three-product stream kernel: complex64, column tiles of
+// 2^min(nn, 6, 12 - nk) >= 32 columns, k tiles of 32, B's three planes of
+// 4-byte entries (at most 2^12 entries per plane).
+bool stream_gauss_shape(int nb, int nm, int nn, int nk, int32_t chunks, int32_t precision) {
+  if (precision != PREC_C64 || nb != 0 || nm < 10 || chunks > 1 || nk < 5 || nk > 7) return false;
+  const int ln = std::min(std::min(nn, 6), 12 - nk);
+  return ln >= 5 && nn - ln <= 10;
+}
+
+int32_t tile_run(int32_t tile, int nb, int nm, int nn, int nk, int32_t chunks, int32_t precision) {
+  if (tile == kGemmStreamGauss) {
+    if (stream_gauss_shape(nb, nm, nn, nk, chunks, precision)) return tile;
+    tile = kGemmStream;
+  }
+  if (tile == kGemmStream) {
+    if (stream_gemm_shape(nb, nm, nn, nk, chunks, precision)) return tile;
+    tile = rule_tile(nn);
+  }
+  return tile;
+}
+
 // Kernel launches of one execution of a step: split-k runs two kernels; a
 // GEMM step runs one launch per 2^23 output tiles (a dispatch holds fewer
 // than 2^32 work-items of 256-thread workgroups).
@@ -476,13 +497,10 @@ static int32_t step_launches(const StepDesc& S, int32_t precision) {
   if (S.kind == KIND_GEMM && S.splitk_chunks > 1) return 2;   // partial tiles, then their sum
   if (S.kind != KIND_GEMM || S.tile < 0 || S.tile >= kNumGemmConfigs) return 1;
   const int nb = (int)S.bA.size(), nm = (int)S.mA.size(), nn = (int)S.nB.size();
-  int tile = S.tile;
-  if (tile == kGemmStream) {
-    if (stream_gemm_shape(nb, nm, nn, (int)S.kA.size(), S.splitk_chunks, precision)) return 1;
-    tile = rule_tile(nn);
-  }
-  static const int lm[kNumGemmConfigs - 1] = {7, 7, 8, 7, 8, 7, 7, 7};   // log2 tile rows
-  static const int ln[kNumGemmConfigs - 1] = {6, 5, 4, 7, 6, 6, 5, 4};   // log2 tile columns
+  const int tile = tile_run(S.tile, nb, nm, nn, (int)S.kA.size(), S.splitk_chunks, precision);
+  if (tile >= kGemmStream) return 1;
+  static const int lm[kGemmStream] = {7, 7, 8, 7, 8, 7, 7, 7};   // log2 tile rows
+  static const int ln[kGemmStream] = {6, 5, 4, 7, 6, 6, 5, 4};   // log2 tile columns
   const int t = nb + std::max(0, nm - lm[tile]) + std::max(0, nn - ln[tile]);
   return t > 23 ? 1 << std::min(t - 23, 24) : 1;
 }

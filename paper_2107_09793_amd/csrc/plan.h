@@ -205,11 +205,20 @@ int32_t choose_kind(int nb, int nm, int nn, int nk, uint32_t flags, int32_t* chu
 // Configuration kGemmStream streams 32-row bands past a B block resident in
 // LDS (few columns and summed values against many rows); a shape it does not
 // take (stream_gemm_shape) runs with the rule's tile configuration instead.
-constexpr int kNumGemmConfigs = 9;
+constexpr int kNumGemmConfigs = 10;
 constexpr int kGemmStream = 8;
+// Configuration kGemmStreamGauss: the stream kernel with three real products
+// per complex product (complex64, column tiles of 32 or 64); a shape it does
+// not take runs as kGemmStream.
+constexpr int kGemmStreamGauss = 9;
 int32_t choose_tile(const Plan& p, int nm, int nn, int nk);
 int32_t rule_tile(int nn);
 bool stream_gemm_shape(int nb, int nm, int nn, int nk, int32_t chunks, int32_t precision);
+bool stream_gauss_shape(int nb, int nm, int nn, int nk, int32_t chunks, int32_t precision);
+// The configuration that runs a GEMM step given configuration `tile`: the
+// stream configurations fall back (9 -> 8 -> the rule's) on shapes they do
+// not take.
+int32_t tile_run(int32_t tile, int nb, int nm, int nn, int nk, int32_t chunks, int32_t precision);
 // Column tile (log2 columns) and k tile (log2 complex k) of the stream kernel.
 void stream_gemm_tile(int nn, int nk, int32_t precision, int* ln, int* lkt);
 

@@ -235,7 +235,7 @@ void launch_stream_cfg(const tnk::StreamGemmArgs& g, unsigned grid, hipStream_t 
                      dim3(64 * tnk::kStreamWaves), 0, st, g);
 }
 
-bool launch_gemm_stream(const tnk::StepArgs& a, int32_t precision, hipStream_t st) {
+bool launch_gemm_stream(const tnk::StepArgs& a, int32_t precision, bool gauss, hipStream_t st) {
   // in-band offsets of A are held in 32 bits
   int64_t band_off = 0;
   for (int j = 0; j < 5; ++j) band_off += (int64_t)1 << a.sA_m[j];
@@ -253,6 +253,10 @@ bool launch_gemm_stream(const tnk::StepArgs& a, int32_t precision, hipStream_t s
   }
   int ln, lkt;
   tn::stream_gemm_tile(a.nn, a.nk, precision, &ln, &lkt);
+  if (gauss) {
+    ln = std::min(std::min(a.nn, 6), 12 - a.nk);
+    lkt = 5;
+  }
   g.a_mask = tile_mask(5, g.s.sA_m, a.nm, lkt, g.s.sA_k, a.nk);
   g.lnt = a.nn - ln;
   g.nbands = 1ull << (a.nm - 5);
@@ -262,6 +266,11 @@ bool launch_gemm_stream(const tnk::StepArgs& a, int32_t precision, hipStream_t s
   while (lg < 8 - g.lnt && (1ull << (lg + 1 + 3)) <= g.nbands) ++lg;
   g.lgroups = lg;
   const unsigned grid = 1u << (lg + g.lnt);
+  if (gauss) {
+    if (ln == 5) launch_stream_cfg<tnk::StreamC64G, 2, 5, 2>(g, grid, st);
+    else launch_stream_cfg<tnk::StreamC64G, 4, 5, 2>(g, grid, st);
+    return true;
+  }
   if (precision == tn::PREC_SPLIT_BF16) {
     switch (ln) {
       case 4: launch_stream_cfg<tnk::StreamSB16, 1, 5, 2>(g, grid, st); break;
@@ -281,9 +290,15 @@ bool launch_gemm_stream(const tnk::StepArgs& a, int32_t precision, hipStream_t s
 
 tn_status launch_gemm(const tnk::StepArgs& a, int32_t precision, int32_t tile, hipStream_t st,
                       int32_t chunks, float2* scratch) {
+  if (tile == tn::kGemmStreamGauss) {
+    if (tn::stream_gauss_shape(a.nb, a.nm, a.nn, a.nk, chunks, precision) &&
+        launch_gemm_stream(a, precision, true, st))
+      return TN_OK;
+    tile = tn::kGemmStream;
+  }
   if (tile == tn::kGemmStream) {
     if (tn::stream_gemm_shape(a.nb, a.nm, a.nn, a.nk, chunks, precision) &&
-        launch_gemm_stream(a, precision, st))
+        launch_gemm_stream(a, precision, false, st))
       return TN_OK;
     tile = tn::rule_tile(a.nn);
   }
@@ -753,6 +768,10 @@ tn_status tn_plan_step(tn_plan_t plan, int32_t step, tn_step_info* out) {
   out->c_bytes = S.c_bytes;
   out->chain = S.chain;
   out->chunks = S.splitk_chunks > 1 ? S.splitk_chunks : 1;
+  out->tile_run = S.kind == tn::KIND_GEMM
+                      ? tn::tile_run(S.tile, (int)S.bA.size(), (int)S.mA.size(), (int)S.nB.size(),
+                                     (int)S.kA.size(), S.splitk_chunks, p.precision)
+                      : -1;
   return TN_OK;
 }
 

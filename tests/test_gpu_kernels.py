@@ -107,11 +107,11 @@ def test_gemm_deterministic_run_to_run(shape):
 
 
 @pytest.mark.parametrize("precision", ["c64", "split_bf16"])
-@pytest.mark.parametrize("cfg", range(9))
+@pytest.mark.parametrize("cfg", range(10))
 def test_every_gemm_tile_config(cfg, precision):
     """Each compiled tile configuration, forced on a full and a partial tile shape
-    (the stream configuration, 8, does not take these shapes and runs them with
-    the rule's configuration)."""
+    (the stream configurations, 8 and 9, do not take these shapes and run them
+    with the rule's configuration)."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2107_09793_amd import Plan
@@ -144,23 +144,27 @@ STREAM_CASES = [
 ]
 
 
+@pytest.mark.parametrize("cfg", [8, 9])
 @pytest.mark.parametrize("precision", ["c64", "split_bf16"])
 @pytest.mark.parametrize("shape", STREAM_CASES, ids=lambda c: "b%dm%dn%dk%dd%d" % c)
-def test_stream_gemm(shape, precision):
+def test_stream_gemm(shape, precision, cfg):
     """The stream configuration (B block resident in LDS, 32-row bands) forced,
     against the oracle: complex64 takes every shape but the batch one;
     split-BF16 (B blocks of at most 2^12 entries, k tiles of 32) takes
     m17n7k6 (two column tiles), m12n5k8 (two), m13n6k5, m11n9k6 (eight) and
-    m10n5k5; the others run with the rule's configuration."""
+    m10n5k5; the others run with the rule's configuration.  Configuration 9
+    (complex64, three real products per complex product, 5 <= nk <= 7) takes
+    m17n7k6 (two column tiles of 64), m13n6k5, m11n9k6 (eight tiles of 64)
+    and m10n5k5 (one tile of 32); the others run as configuration 8."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2107_09793_amd import Plan
     dev = torch.device("cuda:0")
     rng = np.random.default_rng([8, *shape])
     tensors, labels, dims, open_ids = _case(rng, *shape)
-    pl = Plan(labels, dims, open_ids, [(0, 1)], precision=precision, gemm_config=8)
+    pl = Plan(labels, dims, open_ids, [(0, 1)], precision=precision, gemm_config=cfg)
     st = pl.step(0)
-    assert st["kind_name"] == "gemm" and st["tile"] == 8 and st["chunks"] <= 1
+    assert st["kind_name"] == "gemm" and st["tile"] == cfg and st["chunks"] <= 1
     leaves = [torch.from_numpy(t.astype(np.complex64)).to(dev) for t in tensors]
     got = pl.contract(leaves).cpu().numpy()
     x = pl.contract(leaves).cpu().numpy()
@@ -168,15 +172,16 @@ def test_stream_gemm(shape, precision):
     ref = tn_oracle.contract([t.astype(np.complex64).astype(np.complex128) for t in tensors],
                              labels, dims, open_ids, [(0, 1)])
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
-    print("stream", shape, precision, err)
+    print("stream", cfg, shape, precision, err)
     assert err <= (1e-5 if precision == "c64" else 1e-4), err
     if precision == "split_bf16":
         assert err > 1e-9   # really ran in reduced precision
 
 
+@pytest.mark.parametrize("cfg", [8, 9])
 @pytest.mark.parametrize("precision", ["c64", "split_bf16"])
 @pytest.mark.parametrize("shape", [(0, 12, 6, 6, 0), (0, 11, 8, 5, 0)])
-def test_stream_gemm_adjoint(shape, precision):
+def test_stream_gemm_adjoint(shape, precision, cfg):
     """Leaf gradients of a single product C = A B with the stream configuration
     forced: the adjoint step for A, grad_A = grad_C B^H, is a stream-shaped
     GEMM with B conjugated that adds into the gradient buffer.  Reference: the
@@ -187,7 +192,7 @@ def test_stream_gemm_adjoint(shape, precision):
     dev = torch.device("cuda:0")
     rng = np.random.default_rng([9, *shape])
     tensors, labels, dims, open_ids = _case(rng, *shape)
-    pl = Plan(labels, dims, open_ids, [(0, 1)], gemm_config=8, precision=precision)
+    pl = Plan(labels, dims, open_ids, [(0, 1)], gemm_config=cfg, precision=precision)
     leaves = [torch.from_numpy(t.astype(np.complex64)).to(dev) for t in tensors]
     out = pl.contract(leaves)
     w = (rng.standard_normal(out.shape) + 1j * rng.standard_normal(out.shape)).astype(np.complex64)

@@ -387,3 +387,45 @@ def test_invariant_results_reused_across_calls(batch):
         got, _, arena = execute(pl, leaves, arena=arena, start=info["n_invariant"])
         ref = tn_oracle.contract(other.tensors, tn.labels, tn.dims, tn.open, p, sl)
         assert np.allclose(got, np.asarray(ref).reshape(-1), rtol=1e-12)
+
+
+def _pair(nb, nm, nn, nk):
+    """Two tensors A[b, m, k], B[b, k, n] of dimension-2 indices, every free
+    and batch index open: one pairwise step of that shape."""
+    ids = list(range(nb + nm + nn + nk))
+    bat, row = ids[:nb], ids[nb:nb + nm]
+    col, summ = ids[nb + nm:nb + nm + nn], ids[nb + nm + nn:]
+    dims = {i: 2 for i in ids}
+    return [bat + row + summ, bat + summ + col], dims, bat + row + col
+
+
+# (precision, configuration, nb, nm, nn, nk) -> configuration that runs
+STREAM_FALLBACKS = [
+    ("c64", 9, 0, 17, 7, 6, 9), ("c64", 9, 0, 13, 6, 5, 9), ("c64", 9, 0, 11, 9, 6, 9),
+    ("c64", 9, 0, 10, 5, 5, 9),
+    ("c64", 9, 0, 12, 4, 9, 8),       # too many summed values for three products
+    ("c64", 9, 0, 12, 5, 8, 8),
+    ("c64", 9, 0, 11, 7, 4, 8),       # k tile of 32 needs nk >= 5
+    ("c64", 9, 0, 12, 4, 6, 8),       # 16 columns: below a 32-column tile
+    ("c64", 9, 1, 12, 7, 6, 0),       # a batch bit: the rule's 128 x 64
+    ("c64", 8, 0, 12, 4, 9, 8),       # 16 x 512 B entries = 2^13
+    ("c64", 8, 0, 12, 5, 9, 1),       # 2^14 B entries: the rule's 128 x 32
+    ("c64", 8, 0, 9, 6, 6, 0),        # fewer than 2^10 rows
+    ("split_bf16", 9, 0, 17, 7, 6, 8),   # column tiles of 64, 2^12 B entries
+    ("split_bf16", 8, 0, 12, 5, 8, 8),
+    ("split_bf16", 8, 0, 12, 4, 9, 7),   # 2^(12 - 9) columns: below 16
+    ("split_bf16", 8, 0, 11, 7, 4, 0),   # k tile of 32 needs nk >= 5
+]
+
+
+@pytest.mark.parametrize("case", STREAM_FALLBACKS, ids=lambda c: "%s_cfg%d_b%dm%dn%dk%d" % c[:6])
+def test_stream_tile_fallbacks(case):
+    """The stream configurations fall back 9 -> 8 -> the rule's configuration
+    on shapes they do not take; the step reports the one that runs."""
+    precision, cfg, nb, nm, nn, nk, want = case
+    labels, dims, open_ids = _pair(nb, nm, nn, nk)
+    pl = Plan(labels, dims, open_ids, [(0, 1)], precision=precision, gemm_config=cfg)
+    st = pl.step(0)
+    assert st["kind_name"] == "gemm" and st["tile"] == cfg
+    assert (st["nb"], st["nm"], st["nn"], st["nk"]) == (nb, nm, nn, nk)
+    assert st["tile_run"] == want
