@@ -103,7 +103,9 @@ typedef struct {
   int32_t max_resident_bits;  /* cap on log2(slices computed together); -1 = auto   */
   int64_t workspace_limit;    /* bytes the arena may use; 0 = no limit              */
   uint32_t flags;             /* TN_FLAG_*                                          */
-  int32_t gemm_config;        /* -1: per step from the tune table / built-in rule;
+  int32_t gemm_config;        /* -1: per step from the tune table, else the built-in
+                                 rule (steps with >= 2^18 rows: 9 in complex64, 8
+                                 in split-BF16; others by column count);
                                  >= 0: this tile configuration for every GEMM step  */
   const int32_t* tune;        /* n_tune entries of 5 int32 {precision, nm, nn, nk,
                                  config}: measured best tile configuration for GEMM

@@ -436,6 +436,9 @@ int32_t choose_tile(const Plan& p, int nm, int nn, int nk) {
     }
   }
   if (best >= 0) return best;
+  // many rows: the stream kernels (three real products in complex64), which
+  // fall back to the one-tile rule on shapes they do not take
+  if (nm >= 18 && nn >= 4) return p.precision == PREC_C64 ? kGemmStreamGauss : kGemmStream;
   return rule_tile(nn);
 }
 
