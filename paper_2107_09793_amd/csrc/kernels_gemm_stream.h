@@ -254,18 +254,38 @@ struct StreamC64G {
     const int plane = K * NT;
     const float* ar = reinterpret_cast<const float*>(sa) + l31 * 2 + half;
     const float* bp = reinterpret_cast<const float*>(sb) + (kt * (KT / 2) * NT + l31) * 2 + half;
-#pragma unroll 2
-    for (int k2 = 0; k2 < KT / 2; ++k2) {
-      const float a_r = ar[k2 * 64], a_i = ar[kPlane + k2 * 64];
-      const float a_s = a_r + a_i;
+    // operands of k pair k2: Re A, Im A, and per block Re B, Im B, Re B + Im B;
+    // each pair's operands are read while the previous pair's products run
+    float ax[2], bx[3 * NB], ay[2], by[3 * NB];
+    auto operands = [&](int k2, float (&a)[2], float (&b)[3 * NB]) {
+      a[0] = ar[k2 * 64];
+      a[1] = ar[kPlane + k2 * 64];
 #pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const float* bb = bp + (k2 * NT + b * 32) * 2;
-        const float b_r = bb[0], b_i = bb[plane], b_s = bb[2 * plane];
-        acc[3 * b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_r, b_r, acc[3 * b], 0, 0, 0);
-        acc[3 * b + 1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_i, b_i, acc[3 * b + 1], 0, 0, 0);
-        acc[3 * b + 2] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_s, b_s, acc[3 * b + 2], 0, 0, 0);
+      for (int bl = 0; bl < NB; ++bl) {
+        const float* bb = bp + (k2 * NT + bl * 32) * 2;
+        b[3 * bl] = bb[0];
+        b[3 * bl + 1] = bb[plane];
+        b[3 * bl + 2] = bb[2 * plane];
       }
+    };
+    auto products = [&](const float (&a)[2], const float (&b)[3 * NB]) {
+      const float a_s = a[0] + a[1];
+#pragma unroll
+      for (int bl = 0; bl < NB; ++bl) {
+        acc[3 * bl] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0], b[3 * bl], acc[3 * bl], 0, 0, 0);
+        acc[3 * bl + 1] =
+            __builtin_amdgcn_mfma_f32_32x32x2f32(a[1], b[3 * bl + 1], acc[3 * bl + 1], 0, 0, 0);
+        acc[3 * bl + 2] =
+            __builtin_amdgcn_mfma_f32_32x32x2f32(a_s, b[3 * bl + 2], acc[3 * bl + 2], 0, 0, 0);
+      }
+    };
+    operands(0, ax, bx);
+#pragma unroll 1
+    for (int k2 = 0; k2 < KT / 2; k2 += 2) {
+      operands(k2 + 1, ay, by);
+      products(ax, bx);
+      if (k2 + 2 < KT / 2) operands(k2 + 2, ax, bx);
+      products(ay, by);
     }
   }
   // lane holds complex column 32 b + l31 of block b, rows 8 (q / 4) + 4 half
