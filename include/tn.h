@@ -130,7 +130,23 @@ typedef struct {
                                  so a later call with TN_CALL_REUSE_INVARIANT skips
                                  them (Sec. 3.2 shared work, kept across calls)  */
   const int32_t* variable_leaves;
-  int32_t reserved[2];
+  int32_t batch;              /* amplitude batch: 0 or 1 = none; > 1 (a power of
+                                 two) adds one index of dimension batch, id
+                                 n_index, as the leading axis of every leaf in
+                                 batched_leaves (their device buffers hold batch
+                                 variants of the leaf, batch-major) and as the
+                                 leading open index (the output is batch-major):
+                                 entry b is the contraction with every batched
+                                 leaf at its variant b, e.g. the amplitudes of a
+                                 batch of outcomes, which share every step that
+                                 no batched leaf reaches (Sec. 3.2).  Step,
+                                 chain and leaf numbering are unchanged; the
+                                 added index counts in the plan's index ids.
+                                 TN_E_UNSUPPORTED if batch is not a power of two,
+                                 TN_E_INVALID for a leaf id out of range or
+                                 listed twice, or no leaf listed              */
+  int32_t n_batched;
+  const int32_t* batched_leaves;
 } tn_plan_options;
 
 typedef enum { TN_CKPT_AUTO = 0, TN_CKPT_ALL = 1, TN_CKPT_RECOMPUTE = 2 } tn_checkpoint_policy;

@@ -41,7 +41,8 @@ class PlanOptions(ctypes.Structure):
                 ("n_tune", ctypes.c_int32), ("checkpoint_policy", ctypes.c_int32),
                 ("n_variable", ctypes.c_int32),
                 ("variable_leaves", ctypes.POINTER(ctypes.c_int32)),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("batch", ctypes.c_int32), ("n_batched", ctypes.c_int32),
+                ("batched_leaves", ctypes.POINTER(ctypes.c_int32))]
 
 
 class PlanInfo(ctypes.Structure):
@@ -220,7 +221,7 @@ class Plan:
                  max_resident_bits=-1, workspace_limit="auto", no_reuse=False, simple=False,
                  gemm_config=-1, tune="default", persistent=False, chains=True,
                  chain_mfma=True, chain_fused=True, chain_single=True, checkpoint="auto",
-                 fit_backward=False, variable_leaves=()):
+                 fit_backward=False, variable_leaves=(), batch=1, batched_leaves=()):
         n_index = (max(dims) + 1) if isinstance(dims, dict) else len(dims)
         dim_arr = [dims[i] for i in range(n_index)]
         ranks, r_p = _i32([len(l) for l in labels])
@@ -246,6 +247,10 @@ class Plan:
         varr, v_p = _i32(list(variable_leaves) or [0])
         opts.variable_leaves = v_p
         opts.n_variable = len(variable_leaves)
+        barr, b_p = _i32(list(batched_leaves) or [0])
+        opts.batch = int(batch)
+        opts.batched_leaves = b_p
+        opts.n_batched = len(batched_leaves)
         entries = load_tune_table() if tune == "default" else (tune or [])
         tarr, t_p = _i32([x for e in entries for x in e] or [0])
         opts.tune = t_p
@@ -259,6 +264,13 @@ class Plan:
         self.labels = [list(l) for l in labels]
         self.dims = dim_arr
         self.open_ids = list(open_ids)
+        if batch > 1:
+            # the library's added index (id n_index): leading axis of the
+            # batched leaves and leading open index
+            bat = set(int(t) for t in batched_leaves)
+            self.labels = [([n_index] if t in bat else []) + l for t, l in enumerate(self.labels)]
+            self.dims = dim_arr + [int(batch)]
+            self.open_ids = [n_index] + self.open_ids
         self.sliced = list(sliced)
         self.precision = precision
         self.chain_valu = not chain_mfma

@@ -655,6 +655,39 @@ tn_status tn_plan_create(int32_t n_tensors, const int32_t* ranks, const int32_t*
   o.gemm_config = -1;
   if (opts) o = *opts;
   try {
+    // an amplitude batch: one more index, the leading axis of the batched
+    // leaves and the leading open index
+    std::vector<int32_t> b_ranks, b_ids, b_dims, b_open;
+    if (o.batch > 1) {
+      if (o.batch & (o.batch - 1)) return fail(TN_E_UNSUPPORTED, "batch is not a power of two");
+      if (n_tensors < 1 || !ranks || !index_ids || !index_dims || (n_open > 0 && !open_ids))
+        return fail(TN_E_INVALID, "NULL network arrays");
+      if (o.n_batched < 1 || !o.batched_leaves) return fail(TN_E_INVALID, "no batched leaf");
+      std::vector<char> bat(n_tensors, 0);
+      for (int32_t i = 0; i < o.n_batched; ++i) {
+        const int32_t t = o.batched_leaves[i];
+        if (t < 0 || t >= n_tensors || bat[t]) return fail(TN_E_INVALID, "bad batched leaf list");
+        bat[t] = 1;
+      }
+      int64_t pos = 0;
+      for (int32_t t = 0; t < n_tensors; ++t) {
+        if (ranks[t] < 0) return fail(TN_E_INVALID, "negative rank");
+        b_ranks.push_back(ranks[t] + bat[t]);
+        if (bat[t]) b_ids.push_back(n_index);
+        for (int32_t j = 0; j < ranks[t]; ++j) b_ids.push_back(index_ids[pos + j]);
+        pos += ranks[t];
+      }
+      b_dims.assign(index_dims, index_dims + n_index);
+      b_dims.push_back(o.batch);
+      b_open.push_back(n_index);
+      for (int32_t j = 0; j < n_open; ++j) b_open.push_back(open_ids[j]);
+      ranks = b_ranks.data();
+      index_ids = b_ids.data();
+      index_dims = b_dims.data();
+      n_index += 1;
+      open_ids = b_open.data();
+      n_open += 1;
+    }
     tn_plan_s* h = new tn_plan_s();
     bool unsup = false;
     std::string err = tn::build_plan(h->p, n_tensors, ranks, index_ids, n_index, index_dims,

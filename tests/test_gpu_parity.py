@@ -145,6 +145,32 @@ def test_batched_outcomes_match_statevector():
     assert np.max(np.abs(got - ref)) <= 1e-5 * np.max(np.abs(ref))
 
 
+def test_batch_option_matches_statevector():
+    """The same 64 outcomes through tn_plan_options.batch: the network is
+    given without the batch index and the output leaves are flagged as
+    batched (leading axis of 64 variants)."""
+    dev = _dev()
+    circ = circuits.grid_rqc(3, 5, 8, seed=3)
+    batch = circuits.random_bitstrings(15, 2, 64, 3)
+    tn = network.relabel_compact(network.circuit_network(circ, batch=batch))
+    bi = tn.batch_index
+    others = sorted(i for i in tn.dims if i != bi)
+    mp = {i: j for j, i in enumerate(others)}
+    batched = [t for t, l in enumerate(tn.labels) if bi in l]
+    labels = [[mp[i] for i in l if i != bi] for l in tn.labels]
+    dims = {mp[i]: v for i, v in tn.dims.items() if i != bi}
+    p = tpath.greedy_path(tn.labels, tn.dims, tn.open)
+    ts = slicing.TreeSets(tn.labels, tn.dims, tn.open, p)
+    sl = [mp[i] for i in slicing.greedy_slices(ts, n_slice=2)]
+    from paper_2107_09793_amd import Plan
+    pl = Plan(labels, dims, [], p, sl, batch=64, batched_leaves=batched)
+    got = pl.contract(_leaves(tn, dev)).cpu().numpy()
+    assert got.shape == (64,)
+    ref = sv.amplitudes(circ, batch)
+    assert _rel(got, ref) <= 1e-5
+    assert np.max(np.abs(got - ref)) <= 1e-5 * np.max(np.abs(ref))
+
+
 def test_bosonic_small_matches_oracle():
     dev = _dev()
     circ = circuits.gbs_like(2, 4, 2, seed=1, d=4)

@@ -429,3 +429,44 @@ def test_stream_tile_fallbacks(case):
     assert st["kind_name"] == "gemm" and st["tile"] == cfg
     assert (st["nb"], st["nm"], st["nn"], st["nk"]) == (nb, nm, nn, nk)
     assert st["tile_run"] == want
+
+
+def test_amplitude_batch_option_matches_explicit_batch_index():
+    """tn_plan_options.batch / batched_leaves: the library adds the batch index
+    (id n_index) as the leading axis of the listed leaves and the leading open
+    index.  The plan equals the one of the network that carries that index
+    explicitly, and its CPU execution equals the oracle on the same leaves
+    (8 outcomes of a 3x4 circuit, 2 sliced indices)."""
+    tn, p, sl = _batch_net(seed=3, rows=3, cols=4, depth=6, batch=8, n_slice=2)
+    bi = tn.batch_index
+    # move the batch index to the last id, then drop it from the description
+    others = sorted(i for i in tn.dims if i != bi)
+    mp = {i: j for j, i in enumerate(others)}
+    mp[bi] = len(others)
+    labels = [[mp[i] for i in l] for l in tn.labels]
+    dims = {mp[i]: v for i, v in tn.dims.items()}
+    open_ids = [mp[i] for i in tn.open]
+    sliced = [mp[i] for i in sl]
+    bid = mp[bi]
+    assert open_ids == [bid]
+    batched = [t for t, l in enumerate(labels) if bid in l]
+    assert all(labels[t][0] == bid for t in batched)   # leading axis
+    plain_labels = [l[1:] if t in batched else l for t, l in enumerate(labels)]
+    plain_dims = {i: v for i, v in dims.items() if i != bid}
+    explicit = Plan(labels, dims, open_ids, p, sliced)
+    opt = Plan(plain_labels, plain_dims, [], p, sliced, batch=8, batched_leaves=batched)
+    for key in ("n_index", "cmac_reuse", "cmac_noreuse", "n_slices", "arena_bytes", "n_launches"):
+        assert opt.info()[key] == explicit.info()[key], key
+    assert opt.steps() == explicit.steps()
+    assert opt.labels == labels and opt.open_ids == open_ids
+    got, _, _ = execute(opt, tn.tensors)
+    ref = np.asarray(tn_oracle.contract(tn.tensors, tn.labels, tn.dims, tn.open, p, sl)).reshape(-1)
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-14 * np.max(np.abs(ref)))
+    # errors: not a power of two, bad leaf lists
+    with pytest.raises(TnError) as e:
+        Plan(plain_labels, plain_dims, [], p, sliced, batch=6, batched_leaves=batched)
+    assert e.value.status == binding.TN_E_UNSUPPORTED
+    for bad in ([], [batched[0], batched[0]], [len(labels)]):
+        with pytest.raises(TnError) as e:
+            Plan(plain_labels, plain_dims, [], p, sliced, batch=8, batched_leaves=bad)
+        assert e.value.status == binding.TN_E_INVALID
