@@ -402,6 +402,18 @@ def run_precision(args, w, precision, leaves, torch, ws_limit):
         res["rel_err_vs_oracle"] = float(np.max(np.abs(got - ref)) / rms)
         res["rel_err_slices"] = ids
     res["tolerance"] = 1e-5 if precision == "c64" else 1e-3
+    if info["n_segments"] == 0:
+        # the same contraction replayed as a HIP graph (tn_graph_create):
+        # the launch sequence without the per-launch host work
+        g = plan.graph(leaves)
+        g.launch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            g.launch()
+        torch.cuda.synchronize()
+        res["graph_ms_per_step"] = (time.perf_counter() - t0) / args.steps * 1e3
+        del g
     return plan, info, res
 
 
@@ -480,6 +492,9 @@ def main():
         rec["speedup_split_bf16_vs_c64"] = r0["ms_per_step"] / sb["ms_per_step"]
     rec["launches"] = info["n_launches"]
     rec["us_per_amplitude"] = r0["ms_per_step"] * 1e3 / info["out_elems"]
+    if "graph_ms_per_step" in r0:
+        rec["graph_ms_per_step"] = r0["graph_ms_per_step"]
+        rec["graph_us_per_amplitude"] = r0["graph_ms_per_step"] * 1e3 / info["out_elems"]
     if args.cpu_budget > 0:
         print(f"# cpu baseline (oracle, budget {args.cpu_budget:.0f} s)", flush=True)
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)

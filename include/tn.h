@@ -312,6 +312,30 @@ tn_status tn_contract_noalloc(tn_plan_t plan, const void* const* leaves,
                               void* out, void* stream);
 
 /*
+ * A contraction as a HIP graph (the launch sequence of one tn_contract,
+ * captured once and replayed).  tn_graph_create records the kernels that
+ * tn_contract would launch with these arguments -- leaves, slice_ids,
+ * out_mode, out and ws are fixed in the graph: the caller keeps those device
+ * buffers alive and unmoved for the graph's lifetime and may change the
+ * leaves' contents between launches -- and instantiates the graph.  Capture
+ * runs on an internal stream (default priority), so nothing is launched by
+ * tn_graph_create itself; stream is unused and may be NULL.  tn_graph_launch
+ * runs one contraction on `stream`; launches on one workspace must not
+ * overlap.  Same errors as tn_contract, and TN_E_UNSUPPORTED for a plan with
+ * persistent segments (their tables are uploaded from the host on every
+ * call).  For callers that repeat a contraction of fixed shape on new leaf
+ * values (batches of amplitudes, training loops), where per-launch host
+ * overhead dominates small plans.
+ */
+typedef struct tn_graph_s* tn_graph_t;
+tn_status tn_graph_create(tn_plan_t plan, const void* const* leaves, const int64_t* slice_ids,
+                          int64_t n_slice_ids, int32_t out_mode, void* out, void* ws,
+                          size_t ws_bytes, void* stream, tn_graph_t* graph);
+tn_status tn_graph_launch(tn_graph_t graph, void* stream);
+/* Frees the graph; call it after its last launch has completed. */
+void tn_graph_destroy(tn_graph_t graph);
+
+/*
  * Adjoint of tn_contract with out_mode TN_OUT_SUM over the slices
  * slice_ids[n_slice_ids] (NULL, 0 = all; a slice listed twice counts twice):
  * the sum over slices (Eq. sliced_sum) and every pairwise step are linear in

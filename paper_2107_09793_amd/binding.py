@@ -98,7 +98,8 @@ class SegmentLayout(ctypes.Structure):
 EXPORTS = ("tn_plan_create", "tn_plan_query", "tn_plan_step", "tn_contract",
            "tn_contract_probe", "tn_contract_backward", "tn_plan_destroy", "tn_last_error",
            "tn_permute", "tn_plan_chain", "tn_plan_schedule", "tn_plan_segment_tables",
-           "tn_contract_noalloc", "tn_plan_backward_tables", "tn_contract_ex")
+           "tn_contract_noalloc", "tn_plan_backward_tables", "tn_contract_ex",
+           "tn_graph_create", "tn_graph_launch", "tn_graph_destroy")
 TN_CALL_REUSE_INVARIANT = 1
 NOALLOC_WORKSPACE_BYTES = 64 << 20
 
@@ -136,6 +137,14 @@ def lib():
         L.tn_contract_backward.argtypes = [P, ctypes.POINTER(P), P, ctypes.POINTER(P),
                                            ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, P,
                                            ctypes.c_size_t, P]
+        L.tn_graph_create.restype = ctypes.c_int
+        L.tn_graph_create.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.c_int64, ctypes.c_int32, P, P, ctypes.c_size_t, P,
+                                      ctypes.POINTER(P)]
+        L.tn_graph_launch.restype = ctypes.c_int
+        L.tn_graph_launch.argtypes = [P, P]
+        L.tn_graph_destroy.restype = None
+        L.tn_graph_destroy.argtypes = [P]
         L.tn_contract_noalloc.restype = ctypes.c_int
         L.tn_contract_noalloc.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_int64),
                                           ctypes.c_int64, ctypes.c_int32, P, P]
@@ -207,6 +216,26 @@ def load_tune_table(path=TUNE_PATH):
     with open(path) as f:
         doc = json.load(f)
     return [list(map(int, e[:5])) for e in doc.get("entries", [])]
+
+
+class Graph:
+    """An instantiated contraction graph (``tn_graph_create``).  Holds the
+    plan, the leaf tensors, the output and the workspace its kernels use."""
+
+    def __init__(self, handle, plan, leaves, out, ws):
+        self._h, self.plan, self.leaves, self.out, self._ws = handle, plan, leaves, out, ws
+
+    def launch(self, stream=None):
+        """One contraction of the leaves' current contents into ``out``."""
+        _check(lib().tn_graph_launch(self._h, _stream_ptr(stream)))
+        return self.out
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            import torch
+            torch.cuda.synchronize()    # no launch of the graph still running
+            _lib.tn_graph_destroy(self._h)
+            self._h = None
 
 
 class Plan:
@@ -465,6 +494,34 @@ class Plan:
             _check(lib().tn_contract_probe(*args, step, ctypes.c_void_p(e0.cuda_event),
                                            ctypes.c_void_p(e1.cuda_event)))
         return out
+
+    def graph(self, leaves, slice_ids=None, per_slice=False):
+        """``tn_graph_create``: the contraction of these leaf tensors as a HIP
+        graph with its own output (``Graph.out``) on the plan's workspace
+        (shared with ``contract``: calls and launches on one stream run in
+        order); change the leaves in place and call ``Graph.launch()`` to
+        recompute."""
+        import torch
+        inf = self.info()
+        arr, dev = self._leaf_ptrs(leaves)
+        ws = self._workspace(inf["workspace_bytes"], dev, "_ws")
+        self._inv_key = None        # the graph's launches overwrite every result
+        shape = [self.dims[i] for i in self.open_ids]
+        if slice_ids is not None:
+            sids = np.ascontiguousarray(np.asarray(slice_ids, dtype=np.int64))
+            sp = sids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+            nsel = len(sids)
+        else:
+            sids, sp, nsel = None, None, 0
+        rows = (nsel if nsel else inf["n_slices"]) if per_slice else None
+        out = torch.empty(([rows] if per_slice else []) + shape, dtype=torch.complex128,
+                          device=dev)
+        mode = TN_OUT_PER_SLICE if per_slice else TN_OUT_SUM
+        h = ctypes.c_void_p()
+        _check(lib().tn_graph_create(self._h, arr, sp, nsel, mode, ctypes.c_void_p(out.data_ptr()),
+                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(), None,
+                                     ctypes.byref(h)))
+        return Graph(h, self, list(leaves), out, ws)
 
     def contract_noalloc(self, leaves, out, slice_ids=None, per_slice=False, stream=None):
         """``tn_contract_noalloc``: the library's own static workspace, the

@@ -1102,6 +1102,70 @@ static tn_status contract_impl(tn_plan_t plan, const void* const* leaves, const 
   return TN_OK;
 }
 
+struct tn_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~tn_graph_s() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
+tn_status tn_graph_create(tn_plan_t plan, const void* const* leaves, const int64_t* slice_ids,
+                          int64_t n_slice_ids, int32_t out_mode, void* out, void* ws,
+                          size_t ws_bytes, void* stream, tn_graph_t* graph) {
+  (void)stream;
+  if (!graph) return fail(TN_E_INVALID, "graph is NULL");
+  *graph = nullptr;
+  if (!plan) return fail(TN_E_INVALID, "NULL plan");
+  if (!plan->p.segments.empty())
+    return fail(TN_E_UNSUPPORTED, "plans with persistent segments are not captured");
+  hipStream_t cs = nullptr;
+  TN_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  tn_graph_s* g = nullptr;
+  try {
+    g = new tn_graph_s();
+  } catch (const std::bad_alloc&) {
+    (void)hipStreamDestroy(cs);
+    return fail(TN_E_OOM, "host allocation failed");
+  }
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    delete g;
+    (void)hipStreamDestroy(cs);
+    return fail(TN_E_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+  }
+  tn_status s = contract_impl(plan, leaves, slice_ids, n_slice_ids, out_mode, out, ws, ws_bytes,
+                              cs, nullptr);
+  hipGraph_t captured = nullptr;
+  e = hipStreamEndCapture(cs, &captured);   // ends the capture on every path
+  (void)hipStreamDestroy(cs);
+  g->graph = captured;
+  if (s != TN_OK) {
+    delete g;
+    return s;   // tn_last_error holds contract_impl's message
+  }
+  if (e != hipSuccess || !captured) {
+    delete g;
+    return fail(TN_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  }
+  e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    delete g;
+    return fail(TN_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  *graph = g;
+  return TN_OK;
+}
+
+tn_status tn_graph_launch(tn_graph_t graph, void* stream) {
+  if (!graph || !graph->exec) return fail(TN_E_INVALID, "NULL graph");
+  TN_HIP_CHECK(hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream)));
+  return TN_OK;
+}
+
+void tn_graph_destroy(tn_graph_t graph) { delete graph; }
+
 // Workspace of tn_contract_noalloc: a file-scope device array, one copy per
 // GPU the library runs on, held until the process ends.  Host code never
 // passes the array's name to a kernel or a copy: on each device its address
