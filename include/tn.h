@@ -83,6 +83,11 @@ typedef enum { TN_OUT_SUM = 0, TN_OUT_PER_SLICE = 1 } tn_out_mode;
 #define TN_FLAG_FIT_BACKWARD 256u  /* the resident / outer split also keeps
                                      info.workspace_backward_bytes within
                                      workspace_limit (plans used for gradients)      */
+#define TN_FLAG_NO_TINY 512u      /* run tiny steps (at most 2^12 multiply-adds and
+                                     2^10 outputs) one launch each instead of in
+                                     batches of up to 20 consecutive ones per launch
+                                     of one workgroup (batches are formed only
+                                     without TN_FLAG_PERSISTENT)                    */
 #define TN_N_GEMM_CONFIGS 10      /* tile configurations per precision.  8 streams
                                      32-row bands past the whole B block of a column
                                      tile held in LDS: steps with one batch, at least
@@ -222,6 +227,10 @@ typedef struct {
                                  where a stream configuration (8, 9) does not take
                                  the step's shape the one it falls back to (see
                                  TN_N_GEMM_CONFIGS); -1 for other kinds           */
+  int32_t tiny_batch;         /* batch of tiny steps running the step (one launch
+                                 of one workgroup), or -1                         */
+  int32_t tiny_level;         /* its level inside the batch: the steps of one
+                                 level run at once, levels one after another     */
 } tn_step_info;
 
 /* One fused chain as planned (tests).  A chain runs steps first..last (path

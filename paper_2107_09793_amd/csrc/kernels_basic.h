@@ -37,6 +37,67 @@ __global__ void __launch_bounds__(kBlock) k_simple(StepArgs p) {
 }
 
 // ---------------------------------------------------------------------------
+// A batch of tiny steps (consecutive in the schedule, each at most 2^12
+// multiply-adds and 2^10 outputs) in one launch of one workgroup.  The steps
+// come by level (a step's operands are produced by steps of lower levels or
+// before the batch): the outputs of all steps of one level are spread over
+// the workgroup's threads, each formed as k_simple forms it, and a
+// workgroup barrier separates the levels (a level's results are visible to
+// every wave of the workgroup once it is passed).  No workgroup waits on
+// another, and the descriptors travel in the kernel arguments.
+constexpr int kTinyMax = 20;
+constexpr int kTinyClassBits = 14;
+struct TinyStep {
+  const float2* A;
+  const float2* B;
+  float2* C;
+  int8_t nb, nm, nn, nk, level;
+  int8_t sA_b[kTinyClassBits], sB_b[kTinyClassBits], sC_b[kTinyClassBits];
+  int8_t sA_m[kTinyClassBits], sC_m[kTinyClassBits];
+  int8_t sB_n[kTinyClassBits], sC_n[kTinyClassBits];
+  int8_t sA_k[kTinyClassBits], sB_k[kTinyClassBits];
+};
+struct TinyArgs {
+  int32_t n;
+  TinyStep st[kTinyMax];
+};
+static_assert(sizeof(TinyArgs) <= 4000, "kernel arguments");
+
+__global__ void __launch_bounds__(kBlock) k_tiny_run(TinyArgs a) {
+  int s = 0;
+  while (s < a.n) {
+    const int lv = a.st[s].level;
+    int e = s + 1;
+    while (e < a.n && a.st[e].level == lv) ++e;
+    uint32_t total = 0;
+    for (int j = s; j < e; ++j) total += 1u << (a.st[j].nb + a.st[j].nm + a.st[j].nn);
+    for (uint32_t f = threadIdx.x; f < total; f += kBlock) {
+      int j = s;
+      uint32_t o = f;
+      while (o >= (1u << (a.st[j].nb + a.st[j].nm + a.st[j].nn))) {
+        o -= 1u << (a.st[j].nb + a.st[j].nm + a.st[j].nn);
+        ++j;
+      }
+      const TinyStep& T = a.st[j];
+      const int nb = T.nb, nm = T.nm, nn = T.nn, nk = T.nk;
+      const uint32_t K = 1u << nk;
+      const uint32_t n = o & ((1u << nn) - 1);
+      const uint32_t m = (o >> nn) & ((1u << nm) - 1);
+      const uint32_t b = o >> (nn + nm);
+      const int64_t oa = scatter(m, T.sA_m, nm) + scatter(b, T.sA_b, nb);
+      const int64_t ob = scatter(n, T.sB_n, nn) + scatter(b, T.sB_b, nb);
+      const int64_t oc = scatter(n, T.sC_n, nn) + scatter(m, T.sC_m, nm) + scatter(b, T.sC_b, nb);
+      float2 acc = make_float2(0.f, 0.f);
+      for (uint32_t k = 0; k < K; ++k)
+        cfma(acc, T.A[oa + scatter(k, T.sA_k, nk)], T.B[ob + scatter(k, T.sB_k, nk)]);
+      T.C[oc] = acc;
+    }
+    __syncthreads();
+    s = e;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Split-k, pass 1: workgroup (chunk, output) sums 2^chunk_log2 consecutive k
 // values; threads stride by 256 and the workgroup reduces in a fixed tree.
 __global__ void __launch_bounds__(kBlock) k_splitk_partial(StepArgs p) {

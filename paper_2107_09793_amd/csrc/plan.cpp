@@ -679,6 +679,12 @@ static void schedule_pass(Plan& p) {
     S.small = persist && (S.kind == KIND_STREAM || S.kind == KIND_SIMPLE) &&
               S.cmac <= std::ldexp(1.0, 22) && nb <= kSmallClassBits &&
               nm <= kSmallClassBits && nnb <= kSmallClassBits && nk <= kSmallClassBits;
+    // tiny steps (without persistent segments): batches of them run in one
+    // launch of one workgroup (TN_FLAG_NO_TINY: one launch each)
+    S.tiny = !persist && !(p.flags & 512u) && S.kind != KIND_SPLITK && S.splitk_chunks <= 1 &&
+             S.cmac <= std::ldexp(1.0, kTinyCmacBits) && nb + nm + nnb <= kTinyOutBits &&
+             nb <= kTinyClassBits &&
+             nm <= kTinyClassBits && nnb <= kTinyClassBits && nk <= kTinyClassBits;
   }
   // chains: runs of consecutive large stream steps, each consuming the
   // previous result as its large operand, grown while the tile fits
@@ -690,7 +696,7 @@ static void schedule_pass(Plan& p) {
     const bool mfma = !(p.flags & 32u);
     auto fusable = [&](int k) {
       const StepDesc& S = p.steps[k];
-      if (S.small) return false;
+      if (S.small || S.tiny) return false;
       const int nk = (int)S.kA.size(), nn = (int)S.nB.size();
       if (S.kind == KIND_STREAM && nk <= 4 && nn <= 4) return true;
       return mfma && (S.kind == KIND_STREAM || S.kind == KIND_GEMM) && chain_mfma_shape(nk, nn);
@@ -737,7 +743,7 @@ static void schedule_pass(Plan& p) {
       if (p.steps[k].group != ph) continue;
       for (int x : {p.steps[k].a, p.steps[k].b})
         if (x >= n && p.steps[x - n].group == ph) pending[k]++;
-      if (pending[k] == 0) (p.steps[k].small ? rs : rb).push_back(k);
+      if (pending[k] == 0) (p.steps[k].small || p.steps[k].tiny ? rs : rb).push_back(k);
     }
     auto desc = [](std::vector<int32_t>& v) { std::sort(v.begin(), v.end(), std::greater<int32_t>()); };
     desc(rs);
@@ -748,7 +754,7 @@ static void schedule_pass(Plan& p) {
       p.sched.push_back(k);
       int c = consumer[n + k];
       if (c >= 0 && p.steps[c].group == ph && --pending[c] == 0) {
-        (p.steps[c].small ? rs : rb).push_back(c);
+        (p.steps[c].small || p.steps[c].tiny ? rs : rb).push_back(c);
         desc(rs);
         desc(rb);
       }
@@ -779,10 +785,58 @@ static void schedule_pass(Plan& p) {
     }
   }
 
-  // arena.  Steps of one persistent segment run concurrently, so buffers
-  // freed by a segment step are returned only when the whole segment is done.
+  // batches of tiny steps: runs of >= 2 consecutive tiny steps of one group,
+  // at most kTinyMaxSteps per launch (they run in order, so the arena below
+  // needs no change for them)
+  p.tiny_runs.clear();
+  for (size_t i = 0; i < p.sched.size();) {
+    const StepDesc& S = p.steps[p.sched[i]];
+    size_t j = i;
+    while (j < p.sched.size() && j - i < (size_t)kTinyMaxSteps && p.steps[p.sched[j]].tiny &&
+           p.steps[p.sched[j]].group == S.group)
+      ++j;
+    if (j - i >= 2) {
+      p.tiny_runs.push_back(Segment{(int32_t)i, (int32_t)j, 0, S.phase});
+      i = j;
+    } else {
+      i = std::max(j, i + 1);
+    }
+  }
+  // inside a batch the steps run by levels (a step's level: one above the
+  // levels of the batch steps producing its operands), the steps of one
+  // level at once: the batch is reordered by level (still a topological
+  // order)
+  p.tiny_level.assign(p.sched.size(), 0);
+  for (const Segment& g : p.tiny_runs) {
+    std::map<int32_t, int32_t> lvl;   // SSA node produced in the batch -> level
+    std::vector<std::pair<int32_t, int32_t>> ord;   // (level, step)
+    for (int q = g.begin; q < g.end; ++q) {
+      const StepDesc& T = p.steps[p.sched[q]];
+      int32_t L = 0;
+      for (int32_t x : {T.a, T.b}) {
+        auto it = lvl.find(x);
+        if (it != lvl.end()) L = std::max(L, it->second + 1);
+      }
+      lvl[n + p.sched[q]] = L;
+      ord.push_back({L, p.sched[q]});
+    }
+    std::stable_sort(ord.begin(), ord.end(),
+                     [](const std::pair<int32_t, int32_t>& x, const std::pair<int32_t, int32_t>& y) {
+                       return x.first < y.first;
+                     });
+    for (int q = g.begin; q < g.end; ++q) {
+      p.sched[q] = ord[q - g.begin].second;
+      p.tiny_level[q] = (int8_t)std::min(ord[q - g.begin].first, 127);
+    }
+  }
+
+  // arena.  Steps of one persistent segment run concurrently, and so do the
+  // steps of one level of a batch of tiny steps, so buffers freed by such a
+  // step are returned only when the whole segment or batch is done.
   std::vector<int32_t> seg_last(p.sched.size(), -1);   // position -> end of its segment - 1
   for (const Segment& g : p.segments)
+    for (int q = g.begin; q < g.end; ++q) seg_last[q] = g.end - 1;
+  for (const Segment& g : p.tiny_runs)
     for (int q = g.begin; q < g.end; ++q) seg_last[q] = g.end - 1;
   Arena ar;
   p.bytes_no_deletion = 0;
@@ -890,6 +944,13 @@ static void schedule_pass(Plan& p) {
   p.workspace_bytes = align_up(p.arena_bytes, 256) + align_up(p.scratch_bytes, 256) + ctrl + pb;
   // launches: one persistent launch replaces its segment's step launches
   for (const Segment& g : p.segments) {
+    int32_t saved = 0;
+    for (int q = g.begin; q < g.end; ++q) saved += step_launches(p.steps[p.sched[q]], p.precision);
+    int32_t d = saved - 1;
+    p.n_launches -= g.phase ? (int32_t)iters * d : d;
+  }
+  // batches of tiny steps: one launch each
+  for (const Segment& g : p.tiny_runs) {
     int32_t saved = 0;
     for (int q = g.begin; q < g.end; ++q) saved += step_launches(p.steps[p.sched[q]], p.precision);
     int32_t d = saved - 1;

@@ -34,6 +34,7 @@ struct StepDesc {
   int32_t splitk_chunks;
   int32_t tile;           // GEMM tile configuration
   bool small = false;     // runs inside a persistent segment
+  bool tiny = false;      // runs inside a batch of tiny steps (one workgroup)
   int32_t chain = -1;     // chain group this step belongs to
   // 0: invariant (depends on no variable leaf and no outer index; its result
   // may be kept from an earlier call), 1: rest of phase 0, 2: phase 1.
@@ -49,6 +50,13 @@ struct Segment {
 };
 
 constexpr int kSmallClassBits = 24;     // per class, to fit the device descriptor
+constexpr int kTinyMaxSteps = 20;       // steps per batch of tiny steps
+constexpr int kTinyClassBits = 14;      // per class, to fit the kernel arguments
+// a tiny step: at most 2^kTinyCmacBits complex multiply-adds and
+// 2^kTinyOutBits outputs, so that the one workgroup running a batch gives
+// each thread a few outputs (the loads of one output wait on each other)
+constexpr int kTinyCmacBits = 12;
+constexpr int kTinyOutBits = 10;
 constexpr int64_t kSmallStepBytes = 272; // sizeof the device descriptor
 constexpr int64_t kCtrStride = 32;       // int32 slots between completion counters
 
@@ -167,6 +175,8 @@ struct Plan {
   int32_t n_invariant = 0;                   // sched[0 .. n_invariant): invariant steps
   std::vector<uint8_t> leaf_variable;        // leaves that may change between calls
   std::vector<Segment> segments;             // persistent launches
+  std::vector<Segment> tiny_runs;            // batches of tiny steps (schedule positions)
+  std::vector<int8_t> tiny_level;            // per schedule position: level inside its batch
   std::vector<ChainGroup> chains;            // fused chains of stream steps
   std::map<int32_t, std::vector<int32_t>> chain_in_low;  // chain input node -> bits to put lowest
   std::vector<std::vector<int32_t>> chain_sum_bits;      // summed bits of each step

@@ -31,6 +31,8 @@ struct tn_plan_s {
 static_assert(sizeof(tnk::SmallStep) == tn::kSmallStepBytes, "descriptor size");
 static_assert(tnk::kSmallBits == tn::kSmallClassBits, "descriptor bits");
 static_assert(tnk::kCtrStride == tn::kCtrStride, "counter spacing");
+static_assert(tnk::kTinyMax == tn::kTinyMaxSteps && tnk::kTinyClassBits == tn::kTinyClassBits,
+              "batches of tiny steps");
 
 namespace {
 
@@ -401,6 +403,47 @@ tn_status run_step(const Ctx& c, int k, uint64_t outer_val, Probe* probe = nullp
   return s;
 }
 
+// A batch of tiny steps: one launch of one workgroup (k_tiny_run), the steps
+// in the plan's level order.  A probe of one of its steps times the batch.
+tn_status launch_tiny(const Ctx& c, const tn::Segment& g, uint64_t outer_val, Probe* probe) {
+  const tn::Plan& p = c.p;
+  tnk::TinyArgs a;
+  memset(&a, 0, sizeof a);
+  a.n = g.end - g.begin;
+  bool timed = false;
+  for (int q = g.begin; q < g.end; ++q) {
+    const int k = p.sched[q];
+    const tn::StepDesc& S = p.steps[k];
+    tnk::TinyStep& T = a.st[q - g.begin];
+    T.A = node_ptr(c, S.a, outer_val);
+    T.B = node_ptr(c, S.b, outer_val);
+    T.C = reinterpret_cast<float2*>(c.ws + S.c_off);
+    T.nb = (int8_t)S.bA.size();
+    T.nm = (int8_t)S.mA.size();
+    T.nn = (int8_t)S.nB.size();
+    T.nk = (int8_t)S.kA.size();
+    T.level = p.tiny_level[q];
+    copy_bits(T.sA_b, S.bA);
+    copy_bits(T.sB_b, S.bB);
+    copy_bits(T.sC_b, S.bC);
+    copy_bits(T.sA_m, S.mA);
+    copy_bits(T.sC_m, S.mC);
+    copy_bits(T.sB_n, S.nB);
+    copy_bits(T.sC_n, S.nC);
+    copy_bits(T.sA_k, S.kA);
+    copy_bits(T.sB_k, S.kB);
+    timed |= probe && !probe->done && probe->step == k;
+  }
+  if (timed) TN_HIP_CHECK(hipEventRecord(probe->start, c.st));
+  hipLaunchKernelGGL(tnk::k_tiny_run, dim3(1), dim3(tnk::kBlock), 0, c.st, a);
+  TN_HIP_CHECK(hipGetLastError());
+  if (timed) {
+    TN_HIP_CHECK(hipEventRecord(probe->stop, c.st));
+    probe->done = true;
+  }
+  return TN_OK;
+}
+
 // One fused chain (all its steps, one launch).
 // Operand addresses of a launch: node id -> device pointer.
 using NodeSrc = std::function<const float2*(int)>;
@@ -754,10 +797,16 @@ tn_status tn_plan_query(tn_plan_t plan, tn_plan_info* out) {
     double cm = 0;
     int32_t skipped = 0;
     std::vector<uint8_t> chain_done(p.chains.size(), 0);
+    std::vector<int32_t> tiny_end(p.sched.size(), -1);   // batch start -> its end
+    for (const tn::Segment& g : p.tiny_runs) tiny_end[g.begin] = g.end;
     for (int q = 0; q < p.n_invariant; ++q) {
       const tn::StepDesc& S = p.steps[p.sched[q]];
       cm += S.cmac;
-      if (S.chain >= 0 && !(p.flags & 64u)) {   // one launch per fused chain
+      if (tiny_end[q] >= 0) {   // a batch of tiny steps: one launch
+        ++skipped;
+        for (int r = q + 1; r < tiny_end[q]; ++r) cm += p.steps[p.sched[r]].cmac;
+        q = tiny_end[q] - 1;
+      } else if (S.chain >= 0 && !(p.flags & 64u)) {   // one launch per fused chain
         if (!chain_done[S.chain]) ++skipped;
         chain_done[S.chain] = 1;
       } else {
@@ -801,6 +850,14 @@ tn_status tn_plan_step(tn_plan_t plan, int32_t step, tn_step_info* out) {
   out->c_bytes = S.c_bytes;
   out->chain = S.chain;
   out->chunks = S.splitk_chunks > 1 ? S.splitk_chunks : 1;
+  out->tiny_batch = -1;
+  out->tiny_level = 0;
+  for (size_t gi = 0; gi < p.tiny_runs.size(); ++gi)
+    for (int q = p.tiny_runs[gi].begin; q < p.tiny_runs[gi].end; ++q)
+      if (p.sched[q] == step) {
+        out->tiny_batch = (int32_t)gi;
+        out->tiny_level = p.tiny_level[q];
+      }
   out->tile_run = S.kind == tn::KIND_GEMM
                       ? tn::tile_run(S.tile, (int)S.bA.size(), (int)S.mA.size(), (int)S.nB.size(),
                                      (int)S.kA.size(), S.splitk_chunks, p.precision)
@@ -1003,8 +1060,17 @@ static tn_status contract_impl(tn_plan_t plan, const void* const* leaves, const 
     upload.queued = true;
     for (size_t gi = 0; gi < p.segments.size(); ++gi) seg_at[p.segments[gi].begin] = (int32_t)gi;
   }
+  std::vector<int32_t> tiny_at(p.sched.size(), -1);
+  for (size_t ti = 0; ti < p.tiny_runs.size(); ++ti) tiny_at[p.tiny_runs[ti].begin] = (int32_t)ti;
   auto run_range = [&](size_t from, size_t to, uint64_t it) -> tn_status {
     for (size_t i = from; i < to;) {
+      if (tiny_at[i] >= 0) {   // a batch of tiny steps (inside one group, so inside the range)
+        const tn::Segment& g = p.tiny_runs[tiny_at[i]];
+        tn_status s = launch_tiny(c, g, it, probe);
+        if (s != TN_OK) return s;
+        i = g.end;
+        continue;
+      }
       const int32_t gi = seg_at[i];
       if (gi >= 0) {
         const tn::Segment& g = p.segments[gi];

@@ -3,7 +3,9 @@ one by one.  With the chain on the vector units each output value is formed
 by the same complex FMAs in the same order either way, so results must agree
 bit for bit.  With the matrix-core chain steps (the default) the sums run in
 another order, so both are checked against the complex128 oracle (1e-5 of
-the rms slice value)."""
+the rms slice value).  The small networks here are planned without batches
+of tiny steps (tiny=False), which would otherwise take all of their steps
+out of chains."""
 
 import numpy as np
 import pytest
@@ -37,9 +39,9 @@ def test_chain_bitwise_equals_per_step(cfg):
     dev = _dev()
     tn, p, sl = _batch_net(*cfg)
     leaves = [torch.from_numpy(t.astype(np.complex64)).to(dev) for t in tn.tensors]
-    fused = Plan.from_network(tn, p, sl, chain_mfma=False)
-    plain = Plan.from_network(tn, p, sl, chain_mfma=False, chain_fused=False)
-    mfma = Plan.from_network(tn, p, sl)
+    fused = Plan.from_network(tn, p, sl, tiny=False, chain_mfma=False)
+    plain = Plan.from_network(tn, p, sl, tiny=False, chain_mfma=False, chain_fused=False)
+    mfma = Plan.from_network(tn, p, sl, tiny=False)
     assert fused.info()["n_chains"] > 0
     assert plain.info()["n_chains"] == fused.info()["n_chains"]
     assert plain.info()["n_launches"] > fused.info()["n_launches"]
@@ -93,7 +95,7 @@ def test_chain_split_bf16(cfg):
     dev = _dev()
     tn, p, sl = _batch_net(*cfg)
     leaves = [torch.from_numpy(t.astype(np.complex64)).to(dev) for t in tn.tensors]
-    sb = Plan.from_network(tn, p, sl, precision="split_bf16")
+    sb = Plan.from_network(tn, p, sl, tiny=False, precision="split_bf16")
     assert sb.info()["n_chains"] > 0
     assert any(2 <= len(d["kslot"]) <= 6 and 3 <= len(d["nslot"]) <= 5
                and len(d["kslot"]) + len(d["nslot"]) <= 9 and d["nrow"] >= 4
@@ -114,8 +116,8 @@ def test_one_step_chains_bitwise(cfg):
     dev = _dev()
     tn, p, sl = _batch_net(*cfg)
     leaves = [torch.from_numpy(t.astype(np.complex64)).to(dev) for t in tn.tensors]
-    single = Plan.from_network(tn, p, sl, chain_mfma=False)
-    multi = Plan.from_network(tn, p, sl, chain_mfma=False, chain_single=False)
+    single = Plan.from_network(tn, p, sl, tiny=False, chain_mfma=False)
+    multi = Plan.from_network(tn, p, sl, tiny=False, chain_mfma=False, chain_single=False)
     assert any(ch["first"] == ch["last"] for ch in single.chains())
     assert all(ch["first"] < ch["last"] for ch in multi.chains())
     a = single.contract(leaves, per_slice=True).cpu().numpy()

@@ -171,6 +171,29 @@ def test_batch_option_matches_statevector():
     assert np.max(np.abs(got - ref)) <= 1e-5 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("seed", [0, 1])
+def test_batches_of_tiny_steps(seed):
+    """The 3x4 circuit with a batch of 8 outcomes and 2 sliced indices: every
+    slice with tiny steps batched into single-workgroup launches, and with
+    one launch per step, against the oracle (1e-5 of the rms slice)."""
+    dev = _dev()
+    circ = circuits.grid_rqc(3, 4, 8, seed=20 + seed)
+    batch = circuits.random_bitstrings(12, 2, 8, 20 + seed)
+    tn = network.relabel_compact(network.circuit_network(circ, batch=batch))
+    p = tpath.greedy_path(tn.labels, tn.dims, tn.open)
+    sl = slicing.greedy_slices(slicing.TreeSets(tn.labels, tn.dims, tn.open, p), n_slice=2)
+    on = _plan(tn.labels, tn.dims, tn.open, p, sl)
+    off = _plan(tn.labels, tn.dims, tn.open, p, sl, tiny=False)
+    assert on.info()["n_launches"] < off.info()["n_launches"]
+    leaves = _leaves(tn, dev)
+    ref = np.asarray(tn_oracle.contract(tn.tensors, tn.labels, tn.dims, tn.open, p, sl,
+                                        per_slice=True)).reshape(4, -1)
+    rms = np.sqrt(np.mean(np.abs(ref) ** 2))
+    for pl in (on, off):
+        got = pl.contract(leaves, per_slice=True).cpu().numpy().reshape(4, -1)
+        assert np.max(np.abs(got - ref)) <= 1e-5 * rms
+
+
 def test_bosonic_small_matches_oracle():
     dev = _dev()
     circ = circuits.gbs_like(2, 4, 2, seed=1, d=4)

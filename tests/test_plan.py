@@ -175,11 +175,11 @@ def test_cpu_execution_of_fused_chains_matches_oracle(cfg):
     """Chains (consecutive stream steps run as one tiled pass) executed on the
     CPU from their descriptors: tile loads through the input strides, LDS
     slots, per-step small operands selected by passive batch bits, tile
-    stores through the output strides.  Every step outside a persistent
-    segment may join a chain, so small networks have chains with passive and
-    batch bits."""
+    stores through the output strides.  With batches of tiny steps off, every
+    step outside a persistent segment may join a chain, so small networks
+    have chains with passive and batch bits."""
     tn, p, sl = _batch_net(*cfg)
-    pl = Plan.from_network(tn, p, sl, persistent=False)
+    pl = Plan.from_network(tn, p, sl, tiny=False, persistent=False)
     info = pl.info()
     chains = pl.chains()
     assert info["n_chains"] == len(chains) > 0
@@ -201,19 +201,19 @@ def test_cpu_execution_of_fused_chains_matches_oracle(cfg):
     got, _, _ = execute(pl, tn.tensors)
     ref = np.asarray(tn_oracle.contract(tn.tensors, tn.labels, tn.dims, tn.open, p, sl)).reshape(-1)
     assert np.allclose(got, ref, rtol=1e-12, atol=1e-13 * np.max(np.abs(ref)))
-    stepwise = Plan.from_network(tn, p, sl, chain_fused=False)
+    stepwise = Plan.from_network(tn, p, sl, tiny=False, chain_fused=False)
     assert stepwise.info()["n_chains"] == info["n_chains"]
     assert all(s["c_offset"] >= 0 for s in stepwise.steps())
     got2, _, _ = execute(stepwise, tn.tensors)
     assert np.allclose(got2, ref, rtol=1e-12, atol=1e-13 * np.max(np.abs(ref)))
     # lone chainable steps run as one-step chains unless switched off
-    multi = Plan.from_network(tn, p, sl, chain_single=False)
+    multi = Plan.from_network(tn, p, sl, tiny=False, chain_single=False)
     mch = multi.chains()
     assert all(len(ch["st"]) >= 2 for ch in mch)
     assert len(mch) == sum(len(ch["st"]) >= 2 for ch in chains)
     got3, _, _ = execute(multi, tn.tensors)
     assert np.allclose(got3, ref, rtol=1e-12, atol=1e-13 * np.max(np.abs(ref)))
-    unfused = Plan.from_network(tn, p, sl, persistent=False, chains=False)
+    unfused = Plan.from_network(tn, p, sl, tiny=False, persistent=False, chains=False)
     assert unfused.info()["n_chains"] == 0
     assert unfused.info()["n_launches"] - info["n_launches"] == sum(
         ch["last"] - ch["first"] for ch in chains) * (1 << info["n_outer_bits"])
@@ -226,7 +226,7 @@ def test_some_chain_selects_small_operands_by_batch_bits():
     found = False
     for cfg in [(7, 4, 4, 14, 32, 2), (9, 4, 4, 10, 16, 3), (7, 4, 5, 14, 32, 2)]:
         tn, p, sl = _batch_net(*cfg)
-        pl = Plan.from_network(tn, p, sl)
+        pl = Plan.from_network(tn, p, sl, tiny=False)
         found |= any(d["bB"] for ch in pl.chains() for d in ch["st"])
     assert found
 
@@ -240,14 +240,14 @@ def test_chain_descriptors_hold_wide_matrix_core_steps():
     tn = network.relabel_compact(network.circuit_network(circ, batch=b))
     p = tpath.greedy_path(tn.labels, tn.dims, tn.open)
     sl = slicing.greedy_slices(slicing.TreeSets(tn.labels, tn.dims, tn.open, p), n_slice=2)
-    pl = Plan(tn.labels, tn.dims, tn.open, p, sl)
+    pl = Plan(tn.labels, tn.dims, tn.open, p, sl, tiny=False)
     steps = pl.steps()
     wide = [(d, steps[d["step"]]) for ch in pl.chains() for d in ch["st"]
             if steps[d["step"]]["nn"] > 4 or steps[d["step"]]["nk"] > 4]
     assert wide
     for d, s in wide:
         assert len(d["kslot"]) == s["nk"] and len(d["nslot"]) == s["nn"] and d["nrow"] >= 4
-    valu = Plan(tn.labels, tn.dims, tn.open, p, sl, chain_mfma=False)
+    valu = Plan(tn.labels, tn.dims, tn.open, p, sl, tiny=False, chain_mfma=False)
     vsteps = valu.steps()
     for ch in valu.chains():
         for d in ch["st"]:
@@ -285,13 +285,13 @@ def _live_ranges(pl):
 def test_liveness_never_overlaps_live_results(fused):
     if fused:
         tn, p, sl = _batch_net(7, 4, 4, 14, 32, 2)
-        pl = Plan.from_network(tn, p, sl, persistent=False)
+        pl = Plan.from_network(tn, p, sl, tiny=False, persistent=False)
         assert pl.info()["n_chains"] > 0
     else:
         tn, p = _small_net(seed=3, rows=4, cols=4, depth=8)
         ts = slicing.TreeSets(tn.labels, tn.dims, tn.open, p)
         sl = slicing.greedy_slices(ts, n_slice=3)
-        pl = Plan.from_network(tn, p, sl)
+        pl = Plan.from_network(tn, p, sl, tiny=False)
     live = _live_ranges(pl)
     for i in range(len(live)):
         for j in range(i + 1, len(live)):
@@ -470,3 +470,100 @@ def test_amplitude_batch_option_matches_explicit_batch_index():
         with pytest.raises(TnError) as e:
             Plan(plain_labels, plain_dims, [], p, sliced, batch=8, batched_leaves=bad)
         assert e.value.status == binding.TN_E_INVALID
+
+
+def test_batches_of_tiny_steps():
+    """Tiny steps (at most 2^12 multiply-adds and 2^10 outputs, so that one
+    workgroup gives each thread a few outputs) run in batches of up to 20
+    consecutive ones per launch of one workgroup: they never join chains, the
+    batches stay inside one schedule group, the launch count drops by the
+    batched steps, and the CPU execution of the schedule (the order the
+    batches run in) matches the oracle.  TN_FLAG_NO_TINY and persistent
+    segments switch batches off."""
+    tn, p, sl = _batch_net(3, 4, 4, 12, 16, 2)
+    on = Plan.from_network(tn, p, sl)
+    off = Plan.from_network(tn, p, sl, tiny=False)
+    assert on.info()["n_launches"] < off.info()["n_launches"]
+    steps = on.steps()
+    tiny = [k for k, s in enumerate(steps) if s["tiny_batch"] >= 0]
+    assert tiny and all(steps[k]["chain"] < 0 for k in tiny)
+    assert all(steps[k]["cmac"] <= 2 ** 12 and steps[k]["nb"] + steps[k]["nm"] + steps[k]["nn"] <= 10
+               and steps[k]["chunks"] <= 1 and steps[k]["kind_name"] != "splitk" for k in tiny)
+    assert all(s["tiny_batch"] < 0 for s in off.steps())
+    got, _, _ = execute(on, tn.tensors)
+    ref = np.asarray(tn_oracle.contract(tn.tensors, tn.labels, tn.dims, tn.open, p, sl)).reshape(-1)
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-13 * np.max(np.abs(ref)))
+    # the 3x4 circuit of one amplitude: a few launches in all
+    circ = circuits.grid_rqc(3, 4, 8, seed=0)
+    x = circuits.random_bitstrings(12, 2, 1, 0)[0]
+    t1 = network.relabel_compact(network.circuit_network(circ, outcome=x))
+    p1 = tpath.greedy_path(t1.labels, t1.dims, t1.open)
+    a = Plan.from_network(t1, p1)
+    b = Plan.from_network(t1, p1, tiny=False)
+    assert a.info()["n_launches"] <= 16 < b.info()["n_launches"]
+    assert Plan.from_network(t1, p1, persistent=True).info()["n_launches"] == \
+        Plan.from_network(t1, p1, persistent=True, tiny=False).info()["n_launches"]
+
+
+@pytest.mark.parametrize("net", ["batch", "plain", "sliced"])
+def test_tiny_levels_are_safe_to_run_at_once(net):
+    """Inside a batch of tiny steps the steps of one level run at the same
+    time: every operand produced in the batch comes from a lower level, the
+    results of one level overlap neither each other nor any buffer a step of
+    that level reads, and no result overlaps a buffer still to be read later
+    in the batch (the batch's frees are deferred to its end)."""
+    if net == "batch":
+        tn, p, sl = _batch_net(3, 4, 4, 12, 16, 2)
+    else:
+        circ = circuits.grid_rqc(3, 4, 8, seed=4) if net == "plain" else \
+            circuits.grid_rqc(4, 4, 10, seed=4)
+        x = circuits.random_bitstrings(circ.n, 2, 1, 4)[0]
+        tn = network.relabel_compact(network.circuit_network(circ, outcome=x))
+        p = tpath.greedy_path(tn.labels, tn.dims, tn.open)
+        sl = [] if net == "plain" else \
+            slicing.greedy_slices(slicing.TreeSets(tn.labels, tn.dims, tn.open, p), n_slice=3)
+    pl = Plan.from_network(tn, p, sl)
+    steps = pl.steps()
+    n = pl.n_tensors
+    sched = pl.schedule()
+    batches = {}
+    for pos, k in enumerate(sched):
+        b = steps[k]["tiny_batch"]
+        if b >= 0:
+            batches.setdefault(b, []).append((pos, k))
+    assert batches
+    for b, mem in batches.items():
+        pos = [q for q, _ in mem]
+        assert pos == list(range(pos[0], pos[0] + len(pos)))   # consecutive
+        assert 2 <= len(mem) <= 20
+        level = {n + k: steps[k]["tiny_level"] for _, k in mem}
+        levels = [steps[k]["tiny_level"] for _, k in mem]
+        assert levels == sorted(levels)
+
+        def rng(node):
+            s = steps[node - n]
+            return (s["c_offset"], s["c_offset"] + s["c_bytes"])
+
+        def overlap(x, y):
+            return x[0] < y[1] and y[0] < x[1]
+        for _, k in mem:
+            s = steps[k]
+            for x in (s["a"], s["b"]):
+                if x in level:
+                    assert level[x] < s["tiny_level"]
+        for _, k in mem:
+            out = rng(n + k)
+            for _, k2 in mem:
+                if k2 == k:
+                    continue
+                s2 = steps[k2]
+                if s2["tiny_level"] == steps[k]["tiny_level"]:
+                    assert not overlap(out, rng(n + k2))
+                # a later or concurrent reader's operand produced before the batch
+                if s2["tiny_level"] >= steps[k]["tiny_level"]:
+                    for x in (s2["a"], s2["b"]):
+                        if x >= n and x not in level and x != n + k:
+                            assert not overlap(out, rng(x)), (k, k2, x)
+    got, _, _ = execute(pl, tn.tensors)
+    ref = np.asarray(tn_oracle.contract(tn.tensors, tn.labels, tn.dims, tn.open, p, sl)).reshape(-1)
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-13 * np.max(np.abs(ref)))
