@@ -41,7 +41,7 @@ WORKLOAD_DESC = {
     "precision": "53-qubit 6x9 grid (site (0,4) inactive) random circuit, depth 12, "
                  "one amplitude, 10 sliced indices (1024 slices)",
     "bosonic": "16-mode 4x4 lattice, Fock cutoff 4, depth 6, Haar two-mode gates, 16 slices",
-    "gradient": "20-qubit 4x5 grid, depth 10, batch of 256 outcome strings (forward)",
+    "gradient": "20-qubit 4x5 grid, depth 10, batch of 256 outcome strings (forward; forward + backward and the training step in the record's gradient entry)",
     "gbs": "GBS-88-m1: 64-mode 8x8 optical GBS circuit, squeezers r=0.5 + one cycle of "
            "random beam splitters, Fock cutoff 4, one output pattern",
     "gbs8": "GBS-88-m1: 64-mode 8x8 optical GBS circuit, squeezers r=0.5 + one cycle of "
@@ -417,6 +417,53 @@ def run_precision(args, w, precision, leaves, torch, ws_limit):
     return plan, info, res
 
 
+def gradient_step(args, w, plan, leaves, torch):
+    """Timed gradients of the trainable workload (loss = -mean log|amp|^2 over
+    the batch of outcome strings).  ``fwd_bwd``: one ``tn_contract`` plus one
+    ``tn_contract_backward`` (every leaf's gradient) on resident leaves;
+    ``train``: the whole step through torch -- leaves rebuilt from the gate
+    parameters, ``Amplitude.apply``, the loss, and the chain rule back to the
+    parameters."""
+    from paper_2107_09793_amd.autograd import Amplitude, circuit_leaves
+    info = plan.info()
+    grads = [torch.zeros_like(x) for x in leaves]
+    gout = torch.ones(info["out_elems"], dtype=torch.complex128, device=leaves[0].device)
+
+    def fwd_bwd():
+        plan.contract(leaves)
+        plan.backward(leaves, gout, grads)
+
+    params = torch.tensor(w.circuit.params, dtype=torch.float64, requires_grad=True)
+
+    def train():
+        params.grad = None
+        lv = circuit_leaves(w.tn, w.circuit, params, leaves[0].device)
+        amp = Amplitude.apply(plan, *lv)
+        loss = -torch.mean(torch.log(torch.abs(amp) ** 2))
+        loss.backward()
+
+    out = {}
+    for name, fn in (("fwd_bwd", fwd_bwd), ("train", train)):
+        for _ in range(max(1, args.warmup)):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        out[name + "_ms_per_step"] = (time.perf_counter() - t0) / args.steps * 1e3
+    # the adjoint of a step is two products of the step's size (dA = dC B^H,
+    # dB = A^H dC), plus the forward values it recomputes
+    cmac = 3.0 * info["cmac_exec"] + info["cmac_backward_recompute"]
+    out.update(cmac=cmac, value=2.0 * cmac / (out["fwd_bwd_ms_per_step"] * 1e-3) / 1e9,
+               unit="complex GFLOP/s", n_params=int(params.numel()),
+               workspace_backward_bytes=info["workspace_backward_bytes"],
+               backward_policy=info["backward_policy"])
+    print(f"# gradient: forward + backward {out['fwd_bwd_ms_per_step']:.3f} ms, "
+          f"training step {out['train_ms_per_step']:.3f} ms", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -495,6 +542,8 @@ def main():
     if "graph_ms_per_step" in r0:
         rec["graph_ms_per_step"] = r0["graph_ms_per_step"]
         rec["graph_us_per_amplitude"] = r0["graph_ms_per_step"] * 1e3 / info["out_elems"]
+    if getattr(w.circuit, "params", None) is not None and w.batch is not None:
+        rec["gradient"] = gradient_step(args, w, plan, leaves, torch)
     if args.cpu_budget > 0:
         print(f"# cpu baseline (oracle, budget {args.cpu_budget:.0f} s)", flush=True)
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)

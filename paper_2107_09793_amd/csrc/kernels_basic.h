@@ -14,7 +14,6 @@ constexpr int kBlock = 256;
 // persistent executor, so the three agree bit for bit).
 __global__ void __launch_bounds__(kBlock) k_simple(StepArgs p) {
   const uint64_t n_out = 1ull << (p.nb + p.nm + p.nn);
-  const uint64_t K = 1ull << p.nk;
   for (uint64_t o = (uint64_t)blockIdx.x * kBlock + threadIdx.x; o < n_out;
        o += (uint64_t)gridDim.x * kBlock) {
     uint64_t n = o & ((1ull << p.nn) - 1);
@@ -23,10 +22,7 @@ __global__ void __launch_bounds__(kBlock) k_simple(StepArgs p) {
     int64_t oa = scatter(m, p.sA_m, p.nm) + scatter(b, p.sA_b, p.nb);
     int64_t ob = scatter(n, p.sB_n, p.nn) + scatter(b, p.sB_b, p.nb);
     int64_t oc = scatter(n, p.sC_n, p.nn) + scatter(m, p.sC_m, p.nm) + scatter(b, p.sC_b, p.nb);
-    float2 acc = make_float2(0.f, 0.f);
-    for (uint64_t k = 0; k < K; ++k)
-      cfma(acc, maybe_conj(p.A[oa + scatter(k, p.sA_k, p.nk)], p.conjA),
-           maybe_conj(p.B[ob + scatter(k, p.sB_k, p.nk)], p.conjB));
+    float2 acc = dot_k(p.A, oa, p.sA_k, p.conjA, p.B, ob, p.sB_k, p.conjB, p.nk);
     if (p.accumulate) {
       float2 c = p.C[oc];
       acc.x += c.x;
@@ -40,7 +36,8 @@ __global__ void __launch_bounds__(kBlock) k_simple(StepArgs p) {
 // A batch of tiny steps (consecutive in the schedule, each at most 2^12
 // multiply-adds and 2^10 outputs) in one launch of one workgroup.  The steps
 // come by level (a step's operands are produced by steps of lower levels or
-// before the batch): the outputs of all steps of one level are spread over
+// before the batch, and no step writes what another step of its level reads
+// or writes); the outputs of all steps of one level are spread over
 // the workgroup's threads, each formed as k_simple forms it, and a
 // workgroup barrier separates the levels (a level's results are visible to
 // every wave of the workgroup once it is passed).  No workgroup waits on
@@ -52,6 +49,7 @@ struct TinyStep {
   const float2* B;
   float2* C;
   int8_t nb, nm, nn, nk, level;
+  int8_t conjA, conjB, accumulate;   // as in StepArgs
   int8_t sA_b[kTinyClassBits], sB_b[kTinyClassBits], sC_b[kTinyClassBits];
   int8_t sA_m[kTinyClassBits], sC_m[kTinyClassBits];
   int8_t sB_n[kTinyClassBits], sC_n[kTinyClassBits];
@@ -80,16 +78,18 @@ __global__ void __launch_bounds__(kBlock) k_tiny_run(TinyArgs a) {
       }
       const TinyStep& T = a.st[j];
       const int nb = T.nb, nm = T.nm, nn = T.nn, nk = T.nk;
-      const uint32_t K = 1u << nk;
       const uint32_t n = o & ((1u << nn) - 1);
       const uint32_t m = (o >> nn) & ((1u << nm) - 1);
       const uint32_t b = o >> (nn + nm);
       const int64_t oa = scatter(m, T.sA_m, nm) + scatter(b, T.sA_b, nb);
       const int64_t ob = scatter(n, T.sB_n, nn) + scatter(b, T.sB_b, nb);
       const int64_t oc = scatter(n, T.sC_n, nn) + scatter(m, T.sC_m, nm) + scatter(b, T.sC_b, nb);
-      float2 acc = make_float2(0.f, 0.f);
-      for (uint32_t k = 0; k < K; ++k)
-        cfma(acc, T.A[oa + scatter(k, T.sA_k, nk)], T.B[ob + scatter(k, T.sB_k, nk)]);
+      float2 acc = dot_k(T.A, oa, T.sA_k, T.conjA, T.B, ob, T.sB_k, T.conjB, nk);
+      if (T.accumulate) {
+        const float2 c = T.C[oc];
+        acc.x += c.x;
+        acc.y += c.y;
+      }
       T.C[oc] = acc;
     }
     __syncthreads();

@@ -58,4 +58,41 @@ __device__ __forceinline__ float2 maybe_conj(float2 v, int c) {
   return c ? make_float2(v.x, -v.y) : v;
 }
 
+// sum over k < 2^nk of A[oa + off_A(k)] B[ob + off_B(k)] (each operand
+// conjugated on request), accumulated in increasing k.  The operands of 8
+// consecutive k are loaded before their products, so a thread waits on
+// memory once per 8 values of k instead of once per value; the order of the
+// sum is that of the plain loop.
+__device__ __forceinline__ float2 dot_k(const float2* A, int64_t oa, const int8_t* sA_k, int conjA,
+                                        const float2* B, int64_t ob, const int8_t* sB_k, int conjB,
+                                        int nk) {
+  float2 acc = make_float2(0.f, 0.f);
+  if (nk < 3) {
+    for (uint32_t k = 0; k < (1u << nk); ++k)
+      cfma(acc, maybe_conj(A[oa + scatter(k, sA_k, nk)], conjA),
+           maybe_conj(B[ob + scatter(k, sB_k, nk)], conjB));
+    return acc;
+  }
+  int64_t la[8], lb[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    la[u] = scatter(u, sA_k, 3);
+    lb[u] = scatter(u, sB_k, 3);
+  }
+  const uint64_t K = 1ull << nk;
+  for (uint64_t k = 0; k < K; k += 8) {
+    const int64_t ha = oa + scatter_range(k, sA_k, 3, nk);
+    const int64_t hb = ob + scatter_range(k, sB_k, 3, nk);
+    float2 a[8], b[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      a[u] = A[ha + la[u]];
+      b[u] = B[hb + lb[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) cfma(acc, maybe_conj(a[u], conjA), maybe_conj(b[u], conjB));
+  }
+  return acc;
+}
+
 }  // namespace tnk

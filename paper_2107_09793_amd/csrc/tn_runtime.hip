@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <initializer_list>
 #include <map>
 #include <mutex>
 #include <new>
@@ -443,6 +444,115 @@ tn_status launch_tiny(const Ctx& c, const tn::Segment& g, uint64_t outer_val, Pr
   }
   return TN_OK;
 }
+
+// Tiny products issued one after another outside the plan's batches (the
+// adjoint's forward values, recomputations and adjoint products) gathered
+// into k_tiny_run launches.  A product's level is one above that of every
+// earlier product of the batch it conflicts with -- it reads memory that one
+// writes, or writes memory that one reads or writes -- so running the levels
+// in order, all products of a level at once, gives the issue order's results
+// whatever the buffers share.  Any other launch on the stream flushes first.
+class TinyBatcher {
+ public:
+  TinyBatcher(hipStream_t st, bool enabled) : st_(st), enabled_(enabled) {}
+  // true when the product qualifies (the plan's tiny-step limits)
+  bool fits(const tnk::StepArgs& a, int32_t kind, int32_t chunks) const {
+    return enabled_ && kind != tn::KIND_SPLITK && chunks <= 1 && a.nb + a.nm + a.nn <= tn::kTinyOutBits &&
+           a.nb + a.nm + a.nn + a.nk <= tn::kTinyCmacBits && a.nb <= tnk::kTinyClassBits &&
+           a.nm <= tnk::kTinyClassBits && a.nn <= tnk::kTinyClassBits &&
+           a.nk <= tnk::kTinyClassBits;
+  }
+  tn_status add(const tnk::StepArgs& a) {
+    if (n_ == tnk::kTinyMax) {
+      tn_status s = flush();
+      if (s != TN_OK) return s;
+    }
+    Item& it = items_[n_];
+    it.a = a;
+    it.rA = range(a.A, {a.sA_b, a.sA_m, a.sA_k}, {a.nb, a.nm, a.nk});
+    it.rB = range(a.B, {a.sB_b, a.sB_n, a.sB_k}, {a.nb, a.nn, a.nk});
+    it.rC = range(a.C, {a.sC_b, a.sC_m, a.sC_n}, {a.nb, a.nm, a.nn});
+    int lv = 0;
+    for (int i = 0; i < n_; ++i) {
+      const Item& e = items_[i];
+      const bool conflict = meet(e.rC, it.rA) || meet(e.rC, it.rB) || meet(e.rC, it.rC) ||
+                            meet(it.rC, e.rA) || meet(it.rC, e.rB);
+      if (conflict) lv = std::max(lv, e.level + 1);
+    }
+    it.level = lv;
+    ++n_;
+    return TN_OK;
+  }
+  tn_status flush() {
+    if (n_ == 0) return TN_OK;
+    int order[tnk::kTinyMax];
+    for (int i = 0; i < n_; ++i) order[i] = i;
+    std::stable_sort(order, order + n_,
+                     [&](int x, int y) { return items_[x].level < items_[y].level; });
+    tnk::TinyArgs t;
+    memset(&t, 0, sizeof t);
+    t.n = n_;
+    for (int j = 0; j < n_; ++j) {
+      const Item& e = items_[order[j]];
+      tnk::TinyStep& T = t.st[j];
+      T.A = e.a.A;
+      T.B = e.a.B;
+      T.C = e.a.C;
+      T.nb = (int8_t)e.a.nb;
+      T.nm = (int8_t)e.a.nm;
+      T.nn = (int8_t)e.a.nn;
+      T.nk = (int8_t)e.a.nk;
+      T.level = (int8_t)e.level;
+      T.conjA = (int8_t)(e.a.conjA != 0);
+      T.conjB = (int8_t)(e.a.conjB != 0);
+      T.accumulate = (int8_t)(e.a.accumulate != 0);
+      memcpy(T.sA_b, e.a.sA_b, tnk::kTinyClassBits);
+      memcpy(T.sB_b, e.a.sB_b, tnk::kTinyClassBits);
+      memcpy(T.sC_b, e.a.sC_b, tnk::kTinyClassBits);
+      memcpy(T.sA_m, e.a.sA_m, tnk::kTinyClassBits);
+      memcpy(T.sC_m, e.a.sC_m, tnk::kTinyClassBits);
+      memcpy(T.sB_n, e.a.sB_n, tnk::kTinyClassBits);
+      memcpy(T.sC_n, e.a.sC_n, tnk::kTinyClassBits);
+      memcpy(T.sA_k, e.a.sA_k, tnk::kTinyClassBits);
+      memcpy(T.sB_k, e.a.sB_k, tnk::kTinyClassBits);
+    }
+    n_ = 0;
+    ++launches_;
+    hipLaunchKernelGGL(tnk::k_tiny_run, dim3(1), dim3(tnk::kBlock), 0, st_, t);
+    TN_HIP_CHECK(hipGetLastError());
+    return TN_OK;
+  }
+  int64_t launches() const { return launches_; }
+
+ private:
+  struct Range {
+    uintptr_t lo, hi;   // bytes [lo, hi)
+  };
+  struct Item {
+    tnk::StepArgs a;
+    Range rA, rB, rC;
+    int level;
+  };
+  // bytes an operand can touch: its base up to the largest offset its bits
+  // reach (every bit set), plus one entry
+  static Range range(const void* base, std::initializer_list<const int8_t*> s,
+                     std::initializer_list<int> nbits) {
+    uint64_t top = 0;
+    auto b = nbits.begin();
+    for (const int8_t* v : s) {
+      for (int j = 0; j < *b; ++j) top += 1ull << v[j];
+      ++b;
+    }
+    const uintptr_t lo = reinterpret_cast<uintptr_t>(base);
+    return {lo, lo + (top + 1) * sizeof(float2)};
+  }
+  static bool meet(const Range& x, const Range& y) { return x.lo < y.hi && y.lo < x.hi; }
+  hipStream_t st_;
+  bool enabled_;
+  Item items_[tnk::kTinyMax];
+  int n_ = 0;
+  int64_t launches_ = 0;
+};
 
 // One fused chain (all its steps, one launch).
 // Operand addresses of a launch: node id -> device pointer.
@@ -1326,6 +1436,15 @@ tn_status tn_contract_backward(tn_plan_t plan, const void* const* leaves, const 
   float2* scratch = reinterpret_cast<float2*>(W + al256(B.arena_bytes));
   Ctx c{p, leaves, W, scratch, st};
   const int root = n + (n - 1) - 1;
+  // tiny products go out in batches (TN_FLAG_NO_TINY: one launch each)
+  TinyBatcher tb(st, !(p.flags & 512u));
+  auto issue = [&](int32_t kind, int32_t chunks, int32_t tile,
+                   const tnk::StepArgs& a) -> tn_status {
+    if (tb.fits(a, kind, chunks)) return tb.add(a);
+    tn_status s = tb.flush();
+    if (s != TN_OK) return s;
+    return launch_step(kind, chunks, tile, a, scratch, p.precision, st);
+  };
   auto at = [&](int64_t off) { return reinterpret_cast<float2*>(W + off); };
   // value of node x: a leaf (offset for the outer iteration), or the stored /
   // recomputed result (rec: inside a block's adjoint, where values the block
@@ -1346,7 +1465,7 @@ tn_status tn_contract_backward(tn_plan_t plan, const void* const* leaves, const 
     a.A = A;
     a.B = Bp;
     a.C = C;
-    return launch_step(S.kind, S.splitk_chunks, S.tile, a, scratch, p.precision, st);
+    return issue(S.kind, S.splitk_chunks, S.tile, a);
   };
   auto forward = [&](int q0, int q1, uint64_t it) -> tn_status {
     for (int q = q0; q < q1; ++q) {
@@ -1357,7 +1476,9 @@ tn_status tn_contract_backward(tn_plan_t plan, const void* const* leaves, const 
       if (fused) {
         const tn::ChainGroup& g = p.chains[S.chain];
         if (g.last != k) continue;
-        tn_status s = run_chain_with(
+        tn_status s = tb.flush();
+        if (s != TN_OK) return s;
+        s = run_chain_with(
             c, g, [&](int x) -> const float2* { return val(x, it, false); },
             at(B.fwd_off[n + k]), nullptr);
         if (s != TN_OK) return s;
@@ -1369,6 +1490,8 @@ tn_status tn_contract_backward(tn_plan_t plan, const void* const* leaves, const 
     return TN_OK;
   };
   auto fill0 = [&](float2* dst, int64_t elems) -> tn_status {
+    tn_status s = tb.flush();
+    if (s != TN_OK) return s;
     hipLaunchKernelGGL(tnk::k_fill_c64, dim3(grid_for((uint64_t)elems, 1u << 20)),
                        dim3(tnk::kBlock), 0, st, dst, elems);
     TN_HIP_CHECK(hipGetLastError());
@@ -1377,6 +1500,8 @@ tn_status tn_contract_backward(tn_plan_t plan, const void* const* leaves, const 
   // gradient of the root for one outer iteration: the output gradient at
   // every selected resident slice (times its multiplicity), zero elsewhere
   auto root_grad = [&](uint64_t it) -> tn_status {
+    tn_status s = tb.flush();
+    if (s != TN_OK) return s;
     tnk::RootGradArgs rg;
     memset(&rg, 0, sizeof rg);
     rg.grad_out = static_cast<const double2*>(grad_out);
@@ -1392,7 +1517,7 @@ tn_status tn_contract_backward(tn_plan_t plan, const void* const* leaves, const 
       TN_HIP_CHECK(hipGetLastError());
       return TN_OK;
     }
-    tn_status s = fill0(rg.dst, (int64_t)n_all);
+    s = fill0(rg.dst, (int64_t)n_all);
     if (s != TN_OK) return s;
     std::vector<std::pair<int32_t, int32_t>> v(sel[it].begin(), sel[it].end());
     for (size_t i0 = 0; i0 < v.size(); i0 += tnk::kMaxSel) {
@@ -1432,7 +1557,7 @@ tn_status tn_contract_backward(tn_plan_t plan, const void* const* leaves, const 
       int64_t scr;
       int32_t kind = tn::choose_kind(a.nb, a.nm, a.nn, a.nk, p.flags, &ch, &scr);
       int32_t tile = kind == tn::KIND_GEMM ? tn::choose_tile(p, a.nm, a.nn, a.nk) : -1;
-      tn_status s = launch_step(kind, ch, tile, a, scratch, p.precision, st);
+      tn_status s = issue(kind, ch, tile, a);
       if (s != TN_OK) return s;
     }
     if (dB) {
@@ -1451,7 +1576,7 @@ tn_status tn_contract_backward(tn_plan_t plan, const void* const* leaves, const 
       int64_t scr;
       int32_t kind = tn::choose_kind(a.nb, a.nm, a.nn, a.nk, p.flags, &ch, &scr);
       int32_t tile = kind == tn::KIND_GEMM ? tn::choose_tile(p, a.nm, a.nn, a.nk) : -1;
-      tn_status s = launch_step(kind, ch, tile, a, scratch, p.precision, st);
+      tn_status s = issue(kind, ch, tile, a);
       if (s != TN_OK) return s;
     }
     return TN_OK;
@@ -1499,11 +1624,12 @@ tn_status tn_contract_backward(tn_plan_t plan, const void* const* leaves, const 
   } else {
     if (!all && sel.find(0) == sel.end()) {
       // nothing selected: every gradient is zero (leaf gradients unchanged)
-      return TN_OK;
+      return tb.flush();
     }
     if ((s = root_grad(0)) != TN_OK) return s;
   }
-  return adjoint(0, n0, 0);
+  if ((s = adjoint(0, n0, 0)) != TN_OK) return s;
+  return tb.flush();
 }
 
 tn_status tn_permute(const void* in, void* out, int32_t nbits, const int8_t* in_log2,

@@ -166,3 +166,40 @@ def test_full_size_gradient_with_outer_iterations():
     assert info["n_outer_bits"] >= 1
     assert info["workspace_backward_bytes"] <= 20 << 30
     _full_size_directional(pl, wl.tn, seed=4)
+
+
+@pytest.mark.parametrize("policy", ["all", "recompute"])
+def test_backward_tiny_batches(policy):
+    """The adjoint's tiny products (values, recomputations, adjoint products)
+    run in batches of one workgroup, each product one level above the
+    earlier ones of its batch whose memory it shares: the leaf gradients of
+    the trainable workload (256 outcomes, every leaf) equal those of one
+    launch per product within the complex64 tolerance, norm-wise, and leaf
+    gradients accumulate into what the caller passes in."""
+    from paper_2107_09793_amd import Plan
+    dev = _dev()
+    wl = workloads.build("gradient", seed=0)
+    tn = wl.tn
+    leaves = [torch.from_numpy(np.ascontiguousarray(t, dtype=np.complex64)).to(dev)
+              for t in tn.tensors]
+    rng = np.random.default_rng(7)
+    gout = torch.from_numpy(rng.standard_normal(256) + 1j * rng.standard_normal(256)).to(dev)
+    res = {}
+    for tiny in (True, False):
+        pl = Plan.from_network(tn, wl.path, wl.sliced, tiny=tiny, checkpoint=policy)
+        g = [torch.zeros_like(x) for x in leaves]
+        pl.backward(leaves, gout, g)
+        torch.cuda.synchronize()
+        res[tiny] = [x.cpu().numpy().astype(np.complex128) for x in g]
+        if tiny:
+            base = [torch.ones_like(x) for x in leaves]
+            pl.backward(leaves, gout, base)
+            torch.cuda.synchronize()
+            acc = [x.cpu().numpy().astype(np.complex128) for x in base]
+    a = np.concatenate([x.ravel() for x in res[True]])
+    b = np.concatenate([x.ravel() for x in res[False]])
+    err = np.linalg.norm(a - b) / np.linalg.norm(b)
+    print(policy, "tiny batches vs one launch per product:", err)
+    assert err <= 1e-5, err
+    c = np.concatenate([x.ravel() for x in acc]) - 1.0
+    assert np.linalg.norm(c - a) <= 1e-5 * np.linalg.norm(a)
