@@ -421,10 +421,10 @@ def gradient_step(args, w, plan, leaves, torch):
     """Timed gradients of the trainable workload (loss = -mean log|amp|^2 over
     the batch of outcome strings).  ``fwd_bwd``: one ``tn_contract`` plus one
     ``tn_contract_backward`` (every leaf's gradient) on resident leaves;
-    ``train``: the whole step through torch -- leaves rebuilt from the gate
-    parameters, ``Amplitude.apply``, the loss, and the chain rule back to the
-    parameters."""
-    from paper_2107_09793_amd.autograd import Amplitude, circuit_leaves
+    ``train``: the whole step through torch -- the fSim leaves formed from
+    the gate parameters, ``CircuitAmplitude.apply``, the loss, and the chain
+    rule back to the parameters."""
+    from paper_2107_09793_amd.autograd import CircuitAmplitude, CircuitLeaves
     info = plan.info()
     grads = [torch.zeros_like(x) for x in leaves]
     gout = torch.ones(info["out_elems"], dtype=torch.complex128, device=leaves[0].device)
@@ -434,11 +434,11 @@ def gradient_step(args, w, plan, leaves, torch):
         plan.backward(leaves, gout, grads)
 
     params = torch.tensor(w.circuit.params, dtype=torch.float64, requires_grad=True)
+    builder = CircuitLeaves(w.tn, w.circuit, leaves[0].device)
 
     def train():
         params.grad = None
-        lv = circuit_leaves(w.tn, w.circuit, params, leaves[0].device)
-        amp = Amplitude.apply(plan, *lv)
+        amp = CircuitAmplitude.apply(plan, builder, builder.gates(params))
         loss = -torch.mean(torch.log(torch.abs(amp) ** 2))
         loss.backward()
 

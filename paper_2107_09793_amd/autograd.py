@@ -57,3 +57,78 @@ def circuit_leaves(tn, circuit, params, device):
         else:
             out.append(torch.from_numpy(t.astype("complex64")).to(device))
     return out
+
+
+def fsim_batch(theta, phi):
+    """fSim gates of a vector of angles: an (n, 2, 2, 2, 2) complex64 tensor,
+    entry i equal to ``fsim(theta[i], phi[i])``, differentiable in both."""
+    c = torch.cos(theta)
+    s = torch.sin(theta)
+    zero = torch.zeros_like(c)
+    one = torch.ones_like(c)
+    re = torch.stack([one, zero, zero, zero,
+                      zero, c, zero, zero,
+                      zero, zero, c, zero,
+                      zero, zero, zero, torch.cos(phi)], dim=1)
+    im = torch.stack([zero, zero, zero, zero,
+                      zero, zero, -s, zero,
+                      zero, -s, zero, zero,
+                      zero, zero, zero, -torch.sin(phi)], dim=1)
+    return torch.complex(re, im).to(torch.complex64).reshape(-1, 2, 2, 2, 2)
+
+
+class CircuitLeaves:
+    """Leaves of a trainable circuit's network for repeated evaluation: the
+    constant leaves go to the device once; the parameterised fSim leaves are
+    formed from the parameters in one batched expression and travel to the
+    device as one tensor (rows in ``gate_leaf`` order)."""
+
+    def __init__(self, tn, circuit, device):
+        self.device = device
+        self.n = len(tn.tensors)
+        self.gate_leaf, gate_param = [], []
+        self.const = [None] * self.n
+        for j, (t, oi) in enumerate(zip(tn.tensors, tn.leaf_op)):
+            op = circuit.ops[oi]
+            if op.param is not None and t.shape == (2, 2, 2, 2):
+                self.gate_leaf.append(j)
+                gate_param.append(op.param)
+            else:
+                self.const[j] = torch.from_numpy(t.astype("complex64")).to(device)
+        self.gate_param = torch.tensor(gate_param, dtype=torch.long)
+
+    def gates(self, params):
+        """(n_gates, 2, 2, 2, 2) device tensor of the fSim leaves."""
+        p = params[self.gate_param]
+        return fsim_batch(p[:, 0], p[:, 1]).to(self.device)
+
+    def assemble(self, gates):
+        leaves = list(self.const)
+        for i, j in enumerate(self.gate_leaf):
+            leaves[j] = gates[i]
+        return leaves
+
+
+class CircuitAmplitude(torch.autograd.Function):
+    """The contraction as a function of the stacked fSim leaves: forward is
+    tn_contract on the assembled leaves, backward one tn_contract_backward
+    that writes the gate gradients straight into one (n_gates, 2, 2, 2, 2)
+    tensor (no gradients are formed for the constant leaves)."""
+
+    @staticmethod
+    def forward(ctx, plan, builder, gates):
+        ctx.plan = plan
+        ctx.builder = builder
+        ctx.save_for_backward(gates)
+        return plan.contract(builder.assemble(gates))
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (gates,) = ctx.saved_tensors
+        b = ctx.builder
+        g = torch.zeros_like(gates)
+        grads = [None] * b.n
+        for i, j in enumerate(b.gate_leaf):
+            grads[j] = g[i]
+        ctx.plan.backward(b.assemble(gates), grad_out, grads)
+        return None, None, g

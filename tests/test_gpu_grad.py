@@ -203,3 +203,27 @@ def test_backward_tiny_batches(policy):
     assert err <= 1e-5, err
     c = np.concatenate([x.ravel() for x in acc]) - 1.0
     assert np.linalg.norm(c - a) <= 1e-5 * np.linalg.norm(a)
+
+
+def test_circuit_amplitude_parameter_gradients():
+    """The stacked-gate path (CircuitLeaves + CircuitAmplitude: one device
+    tensor of fSim leaves, gate gradients written straight into one tensor)
+    gives the loss and parameter gradient of the state-vector adjoint, twice
+    in a row on the same builder."""
+    from paper_2107_09793_amd import Plan
+    from paper_2107_09793_amd.autograd import CircuitAmplitude, CircuitLeaves
+    dev = _dev()
+    wl = workloads.build("gradient", seed=0)
+    circ, tn = wl.circuit, wl.tn
+    pl = Plan.from_network(tn, wl.path, wl.sliced)
+    builder = CircuitLeaves(tn, circ, dev)
+    ref_loss, g_ref = sv.nll_grad(circ, wl.batch)
+    for _ in range(2):
+        params = torch.tensor(circ.params, dtype=torch.float64, requires_grad=True)
+        amp = CircuitAmplitude.apply(pl, builder, builder.gates(params))
+        loss = -torch.mean(torch.log(torch.abs(amp) ** 2))
+        loss.backward()
+        assert abs(loss.item() - ref_loss) <= 1e-5 * abs(ref_loss)
+        err = np.linalg.norm(params.grad.numpy() - g_ref) / np.linalg.norm(g_ref)
+        print("stacked gates: parameter gradient norm-wise relative error", err)
+        assert err <= 1e-5, err
