@@ -415,6 +415,19 @@ int32_t choose_kind(int nb, int nm, int nn, int nk, uint32_t flags, int32_t* chu
     return KIND_SPLITK;
   }
   if (flags & 2u) return KIND_SIMPLE;
+  if (nk >= 8 && nm >= 5 && nn >= 3 && out_bits - 13 < 8) {
+    // fewer than 2^8 output tiles of 128 x 64 and long sums: chunks of k
+    // bring the launch to about 2^10 workgroups, each chunk summing at least
+    // 2^7 values so that writing and re-reading the partial tiles (16 bytes
+    // per output and chunk) costs less than half the products' time
+    const int tiles_log2 = std::max(0, out_bits - 13);
+    const int cl = std::min(10 - tiles_log2, nk - 7);
+    if (cl >= 1) {
+      *chunks = 1 << cl;
+      *scratch = (int64_t)8 << (out_bits + cl);
+    }
+    return KIND_GEMM;
+  }
   if (nk <= 4 && nn <= 4 && nb <= 12) return KIND_STREAM;
   if (nm >= 5 && nn >= 3 && nk >= 3) return KIND_GEMM;
   // many rows against a few columns and many summed values: the GEMM

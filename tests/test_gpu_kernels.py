@@ -57,6 +57,7 @@ CASES = [
     (1, 6, 5, 14, 0, "gemm"),      # few output tiles, long sums: MFMA tiles split over k
     (0, 5, 3, 12, 0, "gemm"),      # ... with partial tiles
     (0, 7, 4, 9, 1, "gemm"),       # ... dim-4 rows
+    (0, 10, 8, 12, 0, "gemm"),     # 32 tiles of 128x64 against 2^12 summed: 32 chunks of k
     (0, 2, 2, 14, 0, "splitk"),
     (3, 1, 0, 10, 0, "splitk"),
     (0, 3, 3, 6, 0, "simple"),
@@ -75,8 +76,10 @@ def test_pairwise_kernels(case, precision):
     pl = Plan(labels, dims, open_ids, [(0, 1)], precision=precision)
     st = pl.step(0)
     assert st["kind_name"] == kind, st["kind_name"]
-    if kind == "gemm":   # split over k: long sums, few outputs
-        assert (st["chunks"] > 1) == (nk >= 8 and nb + nm + nn + d4 <= 12), st["chunks"]
+    if kind == "gemm":   # split over k: long sums, few output tiles
+        out = nb + nm + nn + d4
+        few_tiles = out - 13 < 8 and min(10 - max(0, out - 13), nk - 7) >= 1
+        assert (st["chunks"] > 1) == (nk >= 8 and (out <= 12 or few_tiles)), st["chunks"]
     dev = torch.device("cuda:0")
     leaves = [torch.from_numpy(t.astype(np.complex64)).to(dev) for t in tensors]
     got = pl.contract(leaves).cpu().numpy()
@@ -134,8 +137,8 @@ STREAM_CASES = [
     # (nb, nm, nn, nk, d4): column blocks of 16, 32, 64, 128; several bands per
     # wave; one k tile per band; column tiles; dim-4 rows; K up to 512
     (0, 17, 7, 6, 0),
-    (0, 12, 4, 9, 0),
-    (0, 12, 5, 8, 0),
+    (0, 17, 4, 9, 0),   # 2^21 outputs: enough tiles that the sum stays whole
+    (0, 16, 5, 8, 0),
     (0, 13, 6, 5, 0),
     (0, 11, 9, 6, 0),
     (0, 10, 7, 4, 1),
@@ -151,7 +154,7 @@ def test_stream_gemm(shape, precision, cfg):
     """The stream configuration (B block resident in LDS, 32-row bands) forced,
     against the oracle: complex64 takes every shape but the batch one;
     split-BF16 (B blocks of at most 2^12 entries, k tiles of 32) takes
-    m17n7k6 (two column tiles), m12n5k8 (two), m13n6k5, m11n9k6 (eight) and
+    m17n7k6 (two column tiles), m16n5k8 (two), m13n6k5, m11n9k6 (eight) and
     m10n5k5; the others run with the rule's configuration.  Configuration 9
     (complex64, three real products per complex product, 5 <= nk <= 7) takes
     m17n7k6 (two column tiles of 64), m13n6k5, m11n9k6 (eight tiles of 64)
