@@ -88,6 +88,12 @@ typedef enum { TN_OUT_SUM = 0, TN_OUT_PER_SLICE = 1 } tn_out_mode;
                                      batches of up to 20 consecutive ones per launch
                                      of one workgroup (batches are formed only
                                      without TN_FLAG_PERSISTENT)                    */
+#define TN_FLAG_GEMM_EMBED 1024u  /* complex64 tiled GEMM steps (configurations 0, 1,
+                                     3-6) use the real embedding of the complex
+                                     product (8 real flops per complex multiply-add)
+                                     instead of three real products (6 flops:
+                                     Re A Re B, Im A Im B, (Re A + Im A)(Re B + Im B))
+                                     */
 #define TN_N_GEMM_CONFIGS 10      /* tile configurations per precision.  8 streams
                                      32-row bands past the whole B block of a column
                                      tile held in LDS: steps with one batch, at least

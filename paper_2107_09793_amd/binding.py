@@ -28,6 +28,7 @@ TN_FLAG_CHAIN_STEPWISE = 64
 TN_FLAG_CHAIN_NO_SINGLE = 128
 TN_FLAG_FIT_BACKWARD = 256
 TN_FLAG_NO_TINY = 512
+TN_FLAG_GEMM_EMBED = 1024
 TN_CKPT_AUTO, TN_CKPT_ALL, TN_CKPT_RECOMPUTE = 0, 1, 2
 _CKPT = {"auto": TN_CKPT_AUTO, "all": TN_CKPT_ALL, "recompute": TN_CKPT_RECOMPUTE}
 KIND_NAMES = {0: "simple", 1: "splitk", 2: "stream", 3: "gemm"}
@@ -252,7 +253,8 @@ class Plan:
                  max_resident_bits=-1, workspace_limit="auto", no_reuse=False, simple=False,
                  gemm_config=-1, tune="default", persistent=False, chains=True,
                  chain_mfma=True, chain_fused=True, chain_single=True, checkpoint="auto",
-                 fit_backward=False, variable_leaves=(), batch=1, batched_leaves=(), tiny=True):
+                 fit_backward=False, variable_leaves=(), batch=1, batched_leaves=(), tiny=True,
+                 gauss=True):
         n_index = (max(dims) + 1) if isinstance(dims, dict) else len(dims)
         dim_arr = [dims[i] for i in range(n_index)]
         ranks, r_p = _i32([len(l) for l in labels])
@@ -272,7 +274,8 @@ class Plan:
             (0 if chain_mfma else TN_FLAG_CHAIN_VALU) | \
             (0 if chain_fused else TN_FLAG_CHAIN_STEPWISE) | \
             (0 if chain_single else TN_FLAG_CHAIN_NO_SINGLE) | \
-            (TN_FLAG_FIT_BACKWARD if fit_backward else 0) | (0 if tiny else TN_FLAG_NO_TINY)
+            (TN_FLAG_FIT_BACKWARD if fit_backward else 0) | (0 if tiny else TN_FLAG_NO_TINY) | \
+            (0 if gauss else TN_FLAG_GEMM_EMBED)
         opts.gemm_config = gemm_config
         opts.checkpoint_policy = _CKPT[checkpoint]
         varr, v_p = _i32(list(variable_leaves) or [0])

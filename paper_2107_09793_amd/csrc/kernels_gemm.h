@@ -226,7 +226,7 @@ struct GemmCommon {
   // 8*(r/4) + 4*(lane/32) + r%4 for accumulator r
   template <int WVN, int WM, int WN>
   __device__ __forceinline__ void epilogue(const StepArgs& p, const GemmTables<MT, NT, KT>& t,
-                                           int64_t cbase, floatx16 (&acc)[WM][WN]) {
+                                           int64_t cbase, floatx16 (&acc)[WM][WN]) const {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wave_m = wave / WVN, wave_n = wave % WVN;
     const int half = lane >> 5, par = lane & 1;
@@ -255,7 +255,8 @@ struct GemmCommon {
 
 // One output tile per workgroup, shared by both precisions.  The tile's first
 // MFMA takes a zero accumulator (Ops::compute<true>).  Ops supplies the LDS
-// staging (lstore) and the MFMA block of one k tile (compute).  (A persistent
+// staging (lstore), the MFMA block of one k tile (compute), the number of
+// accumulator blocks per 32-row block (kAcc) and the epilogue.  (A persistent
 // loop over tiles keeps the epilogue's offsets live across tiles and costs an
 // occupancy step, so each workgroup runs one tile.)
 template <int WVN, int WM, int WN, int MT, int NT, int KT, class OffT, class Ops>
@@ -266,7 +267,7 @@ __device__ __forceinline__ void gemm_tiles(const StepArgs& p, const Strides& S,
   const uint64_t tile = c.tile;
   if (tile >= c.ntiles << c.kc_log2) return;
   float2 ra[GC::AE], rb[GC::BE];
-  floatx16 acc[WM][WN];
+  floatx16 acc[WM][Ops::kAcc];
   c.set_tile(p, S, tile);
   c.gload(p, ra, rb);
   ops.lstore(0, ra, rb);
@@ -290,18 +291,23 @@ __device__ __forceinline__ void gemm_tiles(const StepArgs& p, const Strides& S,
     if (!last) ops.lstore(buf ^ 1, ra, rb);
     __syncthreads();
   }
-  c.template epilogue<WVN, WM, WN>(p, tab, c.baseC, acc);
+  ops.epilogue(p, tab, acc);
 }
 
 // ---------------------------------------------------------------------------
 // complex64 on FP32 MFMA
 template <int WVM, int WVN, int WM, int WN, int MT, int NT, int KT, class GC>
 struct OpsC64 {
+  static constexpr int kAcc = WN;
   float (*sA)[2][KT][MT];
   float2 (*sB)[KT][NT];
   const GC* c;
   float sa, sb;
   int lane, wave_m, wave_n;
+  __device__ __forceinline__ void epilogue(const StepArgs& p, const GemmTables<MT, NT, KT>& t,
+                                           floatx16 (&acc)[WM][WN]) {
+    c->template epilogue<WVN, WM, WN>(p, t, c->baseC, acc);
+  }
   __device__ __forceinline__ void lstore(int buf, const float2* ra, const float2* rb) {
 #pragma unroll
     for (int r = 0; r < GC::AE; ++r) {
@@ -377,6 +383,139 @@ k_gemm_c64(GemmArgs g) {
 }
 
 // ---------------------------------------------------------------------------
+// complex64 with three real products per complex product (Gauss):
+//   T1 = Re A Re B,  T2 = Im A Im B,  T3 = (Re A + Im A)(Re B + Im B),
+//   Re C = T1 - T2,  Im C = T3 - T1 - T2,
+// 6 real flops per complex multiply-add instead of the embedding's 8.  Same
+// LDS staging as OpsC64 (A as Re / Im planes, B as complex entries); one
+// v_mfma_f32_32x32x2f32 covers two complex k for a 32 x 32 complex block
+// (lanes 0-31 the even k, lanes 32-63 the odd one), so a wave's WN 16-column
+// blocks become WN / 2 blocks of 32 complex columns with three accumulators
+// each.
+template <int WVM, int WVN, int WM, int WN, int MT, int NT, int KT, class GC>
+struct OpsC64G {
+  static_assert(WN % 2 == 0 && KT % 2 == 0, "32-column blocks, k pairs");
+  static constexpr int NB = WN / 2;
+  static constexpr int kAcc = 3 * NB;
+  float (*sA)[2][KT][MT];
+  float2 (*sB)[KT][NT];
+  const GC* c;
+  float sa, sb;
+  int lane, wave_m, wave_n;
+  __device__ __forceinline__ void lstore(int buf, const float2* ra, const float2* rb) {
+#pragma unroll
+    for (int r = 0; r < GC::AE; ++r) {
+      const int m = c->a_mk[r] & 0xFFFF, k = c->a_mk[r] >> 16;
+      sA[buf][0][k][m] = ra[r].x;
+      sA[buf][1][k][m] = sa * ra[r].y;
+    }
+#pragma unroll
+    for (int r = 0; r < GC::BE; ++r)
+      sB[buf][c->b_nk[r] >> 16][c->b_nk[r] & 0xFFFF] = make_float2(rb[r].x, sb * rb[r].y);
+  }
+  // one k pair of the tile; ZERO: start from zero accumulators
+  template <bool ZERO>
+  __device__ __forceinline__ void kstep(int buf, int k2, floatx16 (&acc)[WM][kAcc]) {
+    const int k = 2 * k2 + (lane >> 5), l31 = lane & 31;
+    float ar[WM], ai[WM], br[NB], bi[NB];
+#pragma unroll
+    for (int i = 0; i < WM; ++i) {
+      ar[i] = sA[buf][0][k][wave_m * WM * 32 + i * 32 + l31];
+      ai[i] = sA[buf][1][k][wave_m * WM * 32 + i * 32 + l31];
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const float2 bc = sB[buf][k][wave_n * WN * 16 + j * 32 + l31];
+      br[j] = bc.x;
+      bi[j] = bc.y;
+    }
+    const floatx16 zero = {};
+#pragma unroll
+    for (int i = 0; i < WM; ++i) {
+      const float as = ar[i] + ai[i];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        acc[i][3 * j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[i], br[j],
+                                                             ZERO ? zero : acc[i][3 * j], 0, 0, 0);
+        acc[i][3 * j + 1] = __builtin_amdgcn_mfma_f32_32x32x2f32(
+            ai[i], bi[j], ZERO ? zero : acc[i][3 * j + 1], 0, 0, 0);
+        acc[i][3 * j + 2] = __builtin_amdgcn_mfma_f32_32x32x2f32(
+            as, br[j] + bi[j], ZERO ? zero : acc[i][3 * j + 2], 0, 0, 0);
+      }
+    }
+  }
+  template <bool FIRST>
+  __device__ __forceinline__ void compute(int buf, floatx16 (&acc)[WM][kAcc]) {
+    int k0 = 0;
+    if constexpr (FIRST) {
+      kstep<true>(buf, 0, acc);
+      k0 = 1;
+    }
+#pragma unroll 2
+    for (int k2 = k0; k2 < KT / 2; ++k2) kstep<false>(buf, k2, acc);
+  }
+  // lane holds complex column 32 j + (lane & 31) of block j, rows
+  // 8 (r / 4) + 4 (lane / 32) + r % 4 of entry r of its three accumulators
+  __device__ __forceinline__ void epilogue(const StepArgs& p, const GemmTables<MT, NT, KT>& t,
+                                           floatx16 (&acc)[WM][kAcc]) {
+    constexpr int LM = ilog2<MT>::value, LN = ilog2<NT>::value;
+    const int half = lane >> 5, l31 = lane & 31;
+    const int mlim = 1 << (p.nm < LM ? p.nm : LM), nlim = 1 << (p.nn < LN ? p.nn : LN);
+    float2* C = p.C + c->baseC;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int col = wave_n * WN * 16 + j * 32 + l31;
+      if (col >= nlim) continue;
+      const int64_t offn = t.cn[col];
+#pragma unroll
+      for (int i = 0; i < WM; ++i) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = wave_m * WM * 32 + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+          if (row >= mlim) continue;
+          const float t1 = acc[i][3 * j][r], t2 = acc[i][3 * j + 1][r], t3 = acc[i][3 * j + 2][r];
+          float2 v = make_float2(t1 - t2, t3 - t1 - t2);
+          float2* cp = C + offn + t.cm[row];
+          if (p.accumulate) {
+            const float2 o = *cp;
+            v = make_float2(o.x + v.x, o.y + v.y);
+          }
+          *cp = v;
+        }
+      }
+    }
+  }
+};
+
+template <int WVM, int WVN, int WM, int WN, int LK, class OffT>
+__global__ void __launch_bounds__(256) k_gemm_c64g(GemmArgs g) {
+  constexpr int MT = WVM * WM * 32, NT = WVN * WN * 16, KT = 1 << LK;
+  using GC = GemmCommon<MT, NT, KT, OffT>;
+  static_assert(GC::AE >= 1 && GC::BE >= 1, "tile too small for 256 threads");
+  __shared__ float sA[2][2][KT][MT];
+  __shared__ float2 sB[2][KT][NT];
+  __shared__ GemmTables<MT, NT, KT> tab;
+  __shared__ Strides S;
+  const StepArgs& p = g.s;
+  load_strides(p, S);
+  __syncthreads();
+  build_tables<MT, NT, KT>(p, S, tab);
+  __syncthreads();
+  GC c;
+  c.init(g, tab);
+  OpsC64G<WVM, WVN, WM, WN, MT, NT, KT, GC> ops;
+  ops.sA = sA;
+  ops.sB = sB;
+  ops.c = &c;
+  ops.sa = p.conjA ? -1.f : 1.f;
+  ops.sb = p.conjB ? -1.f : 1.f;
+  ops.lane = threadIdx.x & 63;
+  ops.wave_m = (threadIdx.x >> 6) / WVN;
+  ops.wave_n = (threadIdx.x >> 6) % WVN;
+  gemm_tiles<WVN, WM, WN>(p, S, c, tab, ops);
+}
+
+// ---------------------------------------------------------------------------
 // split-BF16 (3 products) on BF16 MFMA with float32 accumulation.  LDS holds
 // the tile already split: A as [m][kr] and the real-embedded B as
 // [real column][kr] (kr = 2 kc + part), hi and lo planes.  Rows are 64 bytes;
@@ -402,11 +541,16 @@ __device__ __forceinline__ void split_pair(float x, float y, uint32_t& hi, uint3
 
 template <int WVM, int WVN, int WM, int WN, int MT, int NT, int KT, class GC>
 struct OpsSB16 {
+  static constexpr int kAcc = WN;
   uint16_t (*sA)[2][MT * 32];
   uint16_t (*sB)[2][2 * NT * 32];
   const GC* c;
   uint32_t ca, cb;   // sign masks for the imaginary half (conjugation)
   int lane, wave_m, wave_n;
+  __device__ __forceinline__ void epilogue(const StepArgs& p, const GemmTables<MT, NT, KT>& t,
+                                           floatx16 (&acc)[WM][WN]) {
+    c->template epilogue<WVN, WM, WN>(p, t, c->baseC, acc);
+  }
   __device__ __forceinline__ void lstore(int buf, const float2* ra, const float2* rb) {
 #pragma unroll
     for (int r = 0; r < GC::AE; ++r) {

@@ -187,7 +187,7 @@ void launch_tiles(uint64_t ntiles, const tnk::GemmArgs& g0, hipStream_t st) {
 
 template <int WVM, int WVN, int WM, int WN, int LK>
 tn_status launch_gemm_cfg(const tnk::StepArgs& a, int32_t precision, hipStream_t st,
-                          int32_t chunks, float2* scratch) {
+                          int32_t chunks, float2* scratch, bool embed) {
   constexpr int MT = WVM * WM * 32, NT = WVN * WN * 16;
   constexpr int LM = tnk::ilog2<MT>::value, LN = tnk::ilog2<NT>::value;
   // split-BF16 tiles always walk k by 16
@@ -218,6 +218,16 @@ tn_status launch_gemm_cfg(const tnk::StepArgs& a, int32_t precision, hipStream_t
   if (precision == tn::PREC_SPLIT_BF16) {
     if (small) launch_tiles<tnk::k_gemm_sb16<WVM, WVN, WM, WN, int32_t>>(nwg, g, st);
     else launch_tiles<tnk::k_gemm_sb16<WVM, WVN, WM, WN, int64_t>>(nwg, g, st);
+  } else if constexpr (WN % 2 == 0) {
+    // complex64: three real products per complex product, unless the real
+    // embedding is asked for (TN_FLAG_GEMM_EMBED)
+    if (!embed) {
+      if (small) launch_tiles<tnk::k_gemm_c64g<WVM, WVN, WM, WN, LK, int32_t>>(nwg, g, st);
+      else launch_tiles<tnk::k_gemm_c64g<WVM, WVN, WM, WN, LK, int64_t>>(nwg, g, st);
+    } else {
+      if (small) launch_tiles<tnk::k_gemm_c64<WVM, WVN, WM, WN, LK, int32_t>>(nwg, g, st);
+      else launch_tiles<tnk::k_gemm_c64<WVM, WVN, WM, WN, LK, int64_t>>(nwg, g, st);
+    }
   } else {
     if (small) launch_tiles<tnk::k_gemm_c64<WVM, WVN, WM, WN, LK, int32_t>>(nwg, g, st);
     else launch_tiles<tnk::k_gemm_c64<WVM, WVN, WM, WN, LK, int64_t>>(nwg, g, st);
@@ -292,7 +302,7 @@ bool launch_gemm_stream(const tnk::StepArgs& a, int32_t precision, bool gauss, h
 }
 
 tn_status launch_gemm(const tnk::StepArgs& a, int32_t precision, int32_t tile, hipStream_t st,
-                      int32_t chunks, float2* scratch) {
+                      int32_t chunks, float2* scratch, bool embed) {
   if (tile == tn::kGemmStreamGauss) {
     if (tn::stream_gauss_shape(a.nb, a.nm, a.nn, a.nk, chunks, precision) &&
         launch_gemm_stream(a, precision, true, st))
@@ -306,21 +316,21 @@ tn_status launch_gemm(const tnk::StepArgs& a, int32_t precision, int32_t tile, h
     tile = tn::rule_tile(a.nn);
   }
   switch (tile) {
-    case 0: return launch_gemm_cfg<2, 2, 2, 2, 4>(a, precision, st, chunks, scratch);   // 128 x 64
-    case 1: return launch_gemm_cfg<4, 1, 1, 2, 4>(a, precision, st, chunks, scratch);   // 128 x 32
-    case 2: return launch_gemm_cfg<4, 1, 2, 1, 4>(a, precision, st, chunks, scratch);   // 256 x 16
-    case 3: return launch_gemm_cfg<2, 2, 2, 4, 4>(a, precision, st, chunks, scratch);   // 128 x 128
-    case 4: return launch_gemm_cfg<2, 2, 4, 2, 4>(a, precision, st, chunks, scratch);   // 256 x 64
-    case 5: return launch_gemm_cfg<2, 2, 2, 2, 5>(a, precision, st, chunks, scratch);   // 128 x 64, k tile 32
-    case 6: return launch_gemm_cfg<4, 1, 1, 2, 3>(a, precision, st, chunks, scratch);   // 128 x 32, k tile 8
-    case 7: return launch_gemm_cfg<4, 1, 1, 1, 4>(a, precision, st, chunks, scratch);   // 128 x 16
+    case 0: return launch_gemm_cfg<2, 2, 2, 2, 4>(a, precision, st, chunks, scratch, embed);   // 128 x 64
+    case 1: return launch_gemm_cfg<4, 1, 1, 2, 4>(a, precision, st, chunks, scratch, embed);   // 128 x 32
+    case 2: return launch_gemm_cfg<4, 1, 2, 1, 4>(a, precision, st, chunks, scratch, embed);   // 256 x 16
+    case 3: return launch_gemm_cfg<2, 2, 2, 4, 4>(a, precision, st, chunks, scratch, embed);   // 128 x 128
+    case 4: return launch_gemm_cfg<2, 2, 4, 2, 4>(a, precision, st, chunks, scratch, embed);   // 256 x 64
+    case 5: return launch_gemm_cfg<2, 2, 2, 2, 5>(a, precision, st, chunks, scratch, embed);   // 128 x 64, k tile 32
+    case 6: return launch_gemm_cfg<4, 1, 1, 2, 3>(a, precision, st, chunks, scratch, embed);   // 128 x 32, k tile 8
+    case 7: return launch_gemm_cfg<4, 1, 1, 1, 4>(a, precision, st, chunks, scratch, embed);   // 128 x 16
     default: return fail(TN_E_INVALID, "unknown GEMM tile configuration");
   }
 }
 
 // Launch one contraction (forward or adjoint) with the given kernel family.
 tn_status launch_step(int32_t kind, int32_t chunks, int32_t tile, const tnk::StepArgs& a0,
-                      float2* scratch, int32_t precision, hipStream_t st) {
+                      float2* scratch, int32_t precision, hipStream_t st, bool embed) {
   tnk::StepArgs a = a0;
   const uint64_t n_out = 1ull << (a.nb + a.nm + a.nn);
   if (kind == tn::KIND_SPLITK) {
@@ -337,7 +347,7 @@ tn_status launch_step(int32_t kind, int32_t chunks, int32_t tile, const tnk::Ste
   } else if (kind == tn::KIND_STREAM && a.nk <= 4 && a.nn <= 4) {
     launch_stream(a, st);
   } else if (kind == tn::KIND_GEMM) {
-    tn_status s = launch_gemm(a, precision, tile, st, chunks, scratch);
+    tn_status s = launch_gemm(a, precision, tile, st, chunks, scratch, embed);
     if (s != TN_OK) return s;
   } else {
     hipLaunchKernelGGL(tnk::k_simple, dim3(grid_for(n_out)), dim3(tnk::kBlock), 0, st, a);
@@ -396,7 +406,8 @@ tn_status run_step(const Ctx& c, int k, uint64_t outer_val, Probe* probe = nullp
   a.C = reinterpret_cast<float2*>(c.ws + S.c_off);
   bool timed = probe && !probe->done && probe->step == k;
   if (timed) TN_HIP_CHECK(hipEventRecord(probe->start, c.st));
-  tn_status s = launch_step(S.kind, S.splitk_chunks, S.tile, a, c.scratch, p.precision, c.st);
+  tn_status s = launch_step(S.kind, S.splitk_chunks, S.tile, a, c.scratch, p.precision, c.st,
+                            (p.flags & 1024u) != 0);
   if (timed && s == TN_OK) {
     TN_HIP_CHECK(hipEventRecord(probe->stop, c.st));
     probe->done = true;
@@ -1443,7 +1454,7 @@ tn_status tn_contract_backward(tn_plan_t plan, const void* const* leaves, const 
     if (tb.fits(a, kind, chunks)) return tb.add(a);
     tn_status s = tb.flush();
     if (s != TN_OK) return s;
-    return launch_step(kind, chunks, tile, a, scratch, p.precision, st);
+    return launch_step(kind, chunks, tile, a, scratch, p.precision, st, (p.flags & 1024u) != 0);
   };
   auto at = [&](int64_t off) { return reinterpret_cast<float2*>(W + off); };
   // value of node x: a leaf (offset for the outer iteration), or the stored /

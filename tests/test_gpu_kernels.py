@@ -217,3 +217,39 @@ def test_stream_gemm_adjoint(shape, precision, cfg):
         got = got.cpu().numpy().astype(np.complex128) - init
         err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
         assert err <= (1e-5 if precision == "c64" else 1e-4), err
+
+
+@pytest.mark.parametrize("cfg", [0, 1, 3, 4, 5, 6])
+@pytest.mark.parametrize("shape", [(0, 9, 7, 6, 0), (1, 7, 6, 9, 0), (0, 6, 5, 5, 1)])
+def test_gemm_three_products_and_embedding(shape, cfg):
+    """complex64 tiled GEMM tiles with three real products per complex product
+    (the default) and with the real embedding (TN_FLAG_GEMM_EMBED), forced
+    tile configuration, against the oracle; full, batched, split-k and
+    partial tiles; and the adjoint (conjugated operands, accumulation) of the
+    three-product kernel against that of the embedding."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2107_09793_amd import Plan
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng([11, cfg, *shape])
+    tensors, labels, dims, open_ids = _case(rng, *shape)
+    ref = tn_oracle.contract([t.astype(np.complex64).astype(np.complex128) for t in tensors],
+                             labels, dims, open_ids, [(0, 1)])
+    leaves = [torch.from_numpy(t.astype(np.complex64)).to(dev) for t in tensors]
+    grads = {}
+    for gauss in (True, False):
+        pl = Plan(labels, dims, open_ids, [(0, 1)], gemm_config=cfg, gauss=gauss)
+        assert pl.step(0)["kind_name"] == "gemm" and pl.step(0)["tile_run"] == cfg
+        got = pl.contract(leaves).cpu().numpy()
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        print("cfg", cfg, shape, "three products" if gauss else "embedding", err)
+        assert err <= 1e-5, err
+        w = torch.from_numpy(rng.standard_normal(got.shape) + 1j * rng.standard_normal(got.shape)
+                             if gauss else grads["w"]).to(dev)
+        if gauss:
+            grads["w"] = w.cpu().numpy()
+        g = [torch.ones_like(x) for x in leaves]
+        pl.backward(leaves, w.reshape(-1), g)
+        grads[gauss] = [x.cpu().numpy().astype(np.complex128) for x in g]
+    for a, b in zip(grads[True], grads[False]):
+        assert np.linalg.norm(a - b) <= 1e-5 * np.linalg.norm(b)
