@@ -100,12 +100,18 @@ def dominant_unit(plan, leaves, info, units, torch):
     return best, execs[best]
 
 
+# complex64 GEMM tile configurations that form three real products per
+# complex product (the others use the real embedding)
+GAUSS_CONFIGS = (0, 1, 3, 4, 5, 6, 9)
+
+
 def roofline(unit, avg_s, precision):
     """The unit's bound is the larger of its HBM time (algorithmic bytes at
     8 TB/s) and its compute time (the MFMA work its kernel executes at the
     precision's peak: 8 real flops per complex multiply-add in the real
-    embedding, 6 with three real products per complex product (GEMM tile
-    configuration 9), three BF16 products of 8 in split-BF16; for chain steps
+    embedding (tile configurations 2, 7 and 8), 6 with three real products
+    per complex product (configuration 9 and the complex64 tiles 0, 1, 3-6),
+    three BF16 products of 8 in split-BF16; for chain steps
     MFMA at the precision's peak or FP32 vector FMA, as the chain runs them;
     FP32 vector FMA for the others).  Achieved is measured in that bound's
     unit: algorithmic bytes, or algorithmic flops (8 per complex multiply-add,
@@ -116,7 +122,8 @@ def roofline(unit, avg_s, precision):
     extra = {}
     if kind == "gemm":
         flops = 8.0 * unit["cmac"]
-        per = 24.0 if precision == "split_bf16" else (6.0 if unit.get("tile_run") == 9 else 8.0)
+        per = 24.0 if precision == "split_bf16" else \
+            (6.0 if unit.get("tile_run") in GAUSS_CONFIGS else 8.0)
         peak, cbound = PEAKS["mfma_" + precision], "mfma"
         t_cmp = per * unit["cmac"] / (peak * 1e12)
         extra = dict(executed_flops_per_cmac=per,
