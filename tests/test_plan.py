@@ -403,17 +403,18 @@ def _pair(nb, nm, nn, nk):
 STREAM_FALLBACKS = [
     ("c64", 9, 0, 17, 7, 6, 9), ("c64", 9, 0, 13, 6, 5, 9), ("c64", 9, 0, 11, 9, 6, 9),
     ("c64", 9, 0, 10, 5, 5, 9),
-    ("c64", 9, 0, 12, 4, 9, 8),       # too many summed values for three products
-    ("c64", 9, 0, 12, 5, 8, 8),
+    ("c64", 9, 0, 17, 4, 9, 8),       # too many summed values for three products
+    ("c64", 9, 0, 16, 5, 8, 8),
     ("c64", 9, 0, 11, 7, 4, 8),       # k tile of 32 needs nk >= 5
     ("c64", 9, 0, 12, 4, 6, 8),       # 16 columns: below a 32-column tile
     ("c64", 9, 1, 12, 7, 6, 0),       # a batch bit: the rule's 128 x 64
-    ("c64", 8, 0, 12, 4, 9, 8),       # 16 x 512 B entries = 2^13
-    ("c64", 8, 0, 12, 5, 9, 1),       # 2^14 B entries: the rule's 128 x 32
+    ("c64", 9, 0, 12, 4, 9, 7),       # few tiles, long sum: split over k, no stream
+    ("c64", 8, 0, 17, 4, 9, 8),       # 16 x 512 B entries = 2^13
+    ("c64", 8, 0, 16, 5, 9, 1),       # 2^14 B entries: the rule's 128 x 32
     ("c64", 8, 0, 9, 6, 6, 0),        # fewer than 2^10 rows
     ("split_bf16", 9, 0, 17, 7, 6, 8),   # column tiles of 64, 2^12 B entries
-    ("split_bf16", 8, 0, 12, 5, 8, 8),
-    ("split_bf16", 8, 0, 12, 4, 9, 7),   # 2^(12 - 9) columns: below 16
+    ("split_bf16", 8, 0, 16, 5, 8, 8),
+    ("split_bf16", 8, 0, 17, 4, 9, 7),   # 2^(12 - 9) columns: below 16
     ("split_bf16", 8, 0, 11, 7, 4, 0),   # k tile of 32 needs nk >= 5
 ]
 
