@@ -282,7 +282,11 @@ __global__ void __launch_bounds__(kBlock) k_permute_plain(PermArgs p) {
 // XOR-swizzled (low half ^= high half) so the strided LDS reads of the write
 // phase spread over banks.  All offsets are XOR/OR-linear in the index bits,
 // so each thread splits them into a per-thread part (its 8 low bits) and a
-// per-element part.
+// per-element part, the latter summed from the strides of the element
+// number's set bits (compile-time) rather than held per element.  The 2^12
+// tile is the kernel's only LDS (the tile-index strides come from the kernel
+// arguments): 32 KiB, so five workgroups share a CU, and the registers fit
+// the five (20 waves per CU in flight).
 struct PermTileArgs {
   const float2* in;
   float2* out;
@@ -303,12 +307,7 @@ __global__ void __launch_bounds__(kBlock) k_permute_tile(PermTileArgs p) {
   static_assert(TB >= 8 && TB <= 16, "tile of 256 threads x E elements");
   constexpr int E = 1 << (TB - 8);
   __shared__ float2 tile[1 << TB];
-  __shared__ int8_t s_tin[kMaxBits], s_tout[kMaxBits];
   const int tid = threadIdx.x;
-  if (tid < kMaxBits) {
-    s_tin[tid] = p.tin[tid];
-    s_tout[tid] = p.tout[tid];
-  }
   // per-thread parts (tile bits 0..7 = thread id bits)
   int64_t in_lo = 0, out_lo = 0;
   uint32_t wl_lo = 0;
@@ -321,45 +320,55 @@ __global__ void __launch_bounds__(kBlock) k_permute_tile(PermTileArgs p) {
   }
   const uint32_t rl_lo = perm_swz((uint32_t)tid, p.half);
   wl_lo = perm_swz(wl_lo, p.half);
-  // per-element parts (tile bits 8.. = element counter e)
-  int64_t in_hi[E], out_hi[E];
-  uint32_t rl_hi[E], wl_hi[E];
+  // per-element parts (tile bits 8.. = element counter e): element e's
+  // offsets are sums of the strides of its set bits
+  int64_t in_b[TB - 8], out_b[TB - 8];
+  uint32_t w_b[TB - 8];
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    int64_t a = 0, c = 0;
-    uint32_t w = 0;
-#pragma unroll 1
-    for (int b = 8; b < TB; ++b) {
-      const int64_t bit = (e >> (b - 8)) & 1;
-      a += bit << p.rin[b];
-      c += bit << p.wout[b];
-      w |= (uint32_t)bit << p.wpos[b];
-    }
-    in_hi[e] = a;
-    out_hi[e] = c;
-    rl_hi[e] = perm_swz((uint32_t)e << 8, p.half);
-    wl_hi[e] = perm_swz(w, p.half);
+  for (int b = 8; b < TB; ++b) {
+    in_b[b - 8] = (int64_t)1 << p.rin[b];
+    out_b[b - 8] = (int64_t)1 << p.wout[b];
+    w_b[b - 8] = 1u << p.wpos[b];
   }
-  __syncthreads();
+  const int half = p.half;
   const uint64_t n_tiles = 1ull << p.rbits;
   for (uint64_t g = blockIdx.x; g < n_tiles; g += gridDim.x) {
     int64_t bin = 0, bout = 0;
 #pragma unroll 1
     for (int b = 0; b < p.rbits; ++b) {
       const int64_t bit = (g >> b) & 1ull;
-      bin += bit << s_tin[b];
-      bout += bit << s_tout[b];
+      bin += bit << p.tin[b];
+      bout += bit << p.tout[b];
     }
     float2 v[E];
+    const int64_t ib = bin + in_lo, ob = bout + out_lo;
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = p.in[bin + in_lo + in_hi[e]];
+    for (int e = 0; e < E; ++e) {
+      int64_t a = 0;
 #pragma unroll
-    for (int e = 0; e < E; ++e) tile[rl_lo ^ rl_hi[e]] = v[e];
+      for (int b = 0; b < TB - 8; ++b)
+        if ((e >> b) & 1) a += in_b[b];
+      v[e] = p.in[ib + a];
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) tile[rl_lo ^ perm_swz((uint32_t)e << 8, half)] = v[e];
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = tile[wl_lo ^ wl_hi[e]];
+    for (int e = 0; e < E; ++e) {
+      uint32_t w = 0;
 #pragma unroll
-    for (int e = 0; e < E; ++e) p.out[bout + out_lo + out_hi[e]] = v[e];
+      for (int b = 0; b < TB - 8; ++b)
+        if ((e >> b) & 1) w |= w_b[b];
+      v[e] = tile[wl_lo ^ perm_swz(w, half)];
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      int64_t c = 0;
+#pragma unroll
+      for (int b = 0; b < TB - 8; ++b)
+        if ((e >> b) & 1) c += out_b[b];
+      p.out[ob + c] = v[e];
+    }
     __syncthreads();
   }
 }
