@@ -86,8 +86,9 @@ typedef enum { TN_OUT_SUM = 0, TN_OUT_PER_SLICE = 1 } tn_out_mode;
 #define TN_FLAG_NO_TINY 512u      /* run tiny steps (at most 2^12 multiply-adds and
                                      2^10 outputs) one launch each instead of in
                                      batches of up to 20 consecutive ones per launch
-                                     of one workgroup (batches are formed only
-                                     without TN_FLAG_PERSISTENT)                    */
+                                     of one workgroup (forward batches are formed
+                                     only without TN_FLAG_PERSISTENT); the same for
+                                     the tiny products of tn_contract_backward      */
 #define TN_FLAG_GEMM_EMBED 1024u  /* complex64 tiled GEMM steps (configurations 0, 1,
                                      3-6) use the real embedding of the complex
                                      product (8 real flops per complex multiply-add)
