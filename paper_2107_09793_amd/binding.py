@@ -305,6 +305,11 @@ class Plan:
             self.labels = [([n_index] if t in bat else []) + l for t, l in enumerate(self.labels)]
             self.dims = dim_arr + [int(batch)]
             self.open_ids = [n_index] + self.open_ids
+        # elements of each leaf, checked on every call
+        self._leaf_numel = [int(np.prod([self.dims[i] for i in l], dtype=np.int64))
+                            for l in self.labels]
+        self._ptr_array = ctypes.c_void_p * self.n_tensors
+        self._info = None         # tn_plan_query, fixed for the plan's life
         self.sliced = list(sliced)
         self.precision = precision
         self.chain_valu = not chain_mfma
@@ -323,6 +328,11 @@ class Plan:
         if h is not None and h.value and _lib is not None:
             _lib.tn_plan_destroy(h)
             self._h = None
+
+    def _static_info(self):
+        if self._info is None:
+            self._info = self.info()
+        return self._info
 
     def info(self):
         inf = PlanInfo()
@@ -436,13 +446,15 @@ class Plan:
         if len(leaves) != self.n_tensors:
             raise ValueError(f"expected {self.n_tensors} leaves, got {len(leaves)}")
         dev = leaves[0].device
+        c64, numel = torch.complex64, self._leaf_numel
+        ptrs = []
         for t, x in enumerate(leaves):
-            if x.dtype != torch.complex64 or not x.is_contiguous() or x.device != dev:
+            if x.dtype != c64 or not x.is_contiguous() or x.device != dev:
                 raise ValueError(f"leaf {t} must be a contiguous complex64 tensor on {dev}")
-            if x.numel() != int(np.prod([self.dims[i] for i in self.labels[t]], dtype=np.int64)):
+            if x.numel() != numel[t]:
                 raise ValueError(f"leaf {t} has {x.numel()} elements, network says otherwise")
-        arr = (ctypes.c_void_p * self.n_tensors)(*[x.data_ptr() for x in leaves])
-        return arr, dev
+            ptrs.append(x.data_ptr())
+        return self._ptr_array(*ptrs), dev
 
     def _invariant_key(self, leaves, ws):
         """Key of the invariant leaves' contents: each tensor's identity and
@@ -461,7 +473,7 @@ class Plan:
         leaves are the same tensors, unmodified, as in the previous call on
         this workspace (``reuse_invariant``)."""
         import torch
-        inf = self.info()
+        inf = self._static_info()
         arr, dev = self._leaf_ptrs(leaves)
         ws = self._workspace(inf["workspace_bytes"], dev, "_ws")
         flags = 0
@@ -507,7 +519,7 @@ class Plan:
         order); change the leaves in place and call ``Graph.launch()`` to
         recompute."""
         import torch
-        inf = self.info()
+        inf = self._static_info()
         arr, dev = self._leaf_ptrs(leaves)
         ws = self._workspace(inf["workspace_bytes"], dev, "_ws")
         self._inv_key = None        # the graph's launches overwrite every result
@@ -547,7 +559,7 @@ class Plan:
         """Adds d(loss)/d(leaf) (PyTorch convention) into ``grad_leaves`` for
         the output summed over ``slice_ids`` (None = all slices)."""
         import torch
-        inf = self.info()
+        inf = self._static_info()
         arr, dev = self._leaf_ptrs(leaves)
         ws = self._workspace(inf["workspace_backward_bytes"], dev, "_ws_bwd")
         g = grad_out.to(torch.complex128).contiguous()
