@@ -61,7 +61,19 @@ struct TinyArgs {
 };
 static_assert(sizeof(TinyArgs) <= 4000, "kernel arguments");
 
-__global__ void __launch_bounds__(kBlock) k_tiny_run(TinyArgs a) {
+static_assert(sizeof(TinyArgs) % 4 == 0, "descriptor copy in 32-bit words");
+
+__global__ void __launch_bounds__(kBlock) k_tiny_run(TinyArgs args) {
+  // the descriptors go to LDS once: every output of every level looks up its
+  // step's sizes and strides, and from the kernel arguments (indexed per
+  // thread) each lookup would be a dependent memory round trip
+  __shared__ TinyArgs a;
+  {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(&args);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&a);
+    for (int i = threadIdx.x; i < (int)(sizeof(TinyArgs) / 4); i += kBlock) dst[i] = src[i];
+  }
+  __syncthreads();
   int s = 0;
   while (s < a.n) {
     const int lv = a.st[s].level;
