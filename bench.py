@@ -428,6 +428,8 @@ def gradient_step(args, w, plan, leaves, torch):
     """Timed gradients of the trainable workload (loss = -mean log|amp|^2 over
     the batch of outcome strings).  ``fwd_bwd``: one ``tn_contract`` plus one
     ``tn_contract_backward`` (every leaf's gradient) on resident leaves;
+    ``fwd_bwd_graph``: the same two calls replayed as HIP graphs
+    (``tn_graph_create``, ``tn_graph_create_backward``);
     ``train``: the whole step through torch -- the fSim leaves formed from
     the gate parameters, ``CircuitAmplitude.apply``, the loss, and the chain
     rule back to the parameters."""
@@ -449,8 +451,16 @@ def gradient_step(args, w, plan, leaves, torch):
         loss = -torch.mean(torch.log(torch.abs(amp) ** 2))
         loss.backward()
 
+    # the same forward + backward replayed as two HIP graphs
+    fg = plan.graph(leaves)
+    bg = plan.backward_graph(leaves, gout, grads)
+
+    def fwd_bwd_graph():
+        fg.launch()
+        bg.launch()
+
     out = {}
-    for name, fn in (("fwd_bwd", fwd_bwd), ("train", train)):
+    for name, fn in (("fwd_bwd", fwd_bwd), ("fwd_bwd_graph", fwd_bwd_graph), ("train", train)):
         for _ in range(max(1, args.warmup)):
             fn()
         torch.cuda.synchronize()
@@ -466,7 +476,9 @@ def gradient_step(args, w, plan, leaves, torch):
                unit="complex GFLOP/s", n_params=int(params.numel()),
                workspace_backward_bytes=info["workspace_backward_bytes"],
                backward_policy=info["backward_policy"])
-    print(f"# gradient: forward + backward {out['fwd_bwd_ms_per_step']:.3f} ms, "
+    del fg, bg
+    print(f"# gradient: forward + backward {out['fwd_bwd_ms_per_step']:.3f} ms "
+          f"({out['fwd_bwd_graph_ms_per_step']:.3f} ms as graphs), "
           f"training step {out['train_ms_per_step']:.3f} ms", file=sys.stderr, flush=True)
     return out
 

@@ -350,6 +350,22 @@ tn_status tn_graph_create(tn_plan_t plan, const void* const* leaves, const int64
 tn_status tn_graph_launch(tn_graph_t graph, void* stream);
 /* Frees the graph; call it after its last launch has completed. */
 void tn_graph_destroy(tn_graph_t graph);
+/*
+ * The adjoint as a HIP graph: records the kernels tn_contract_backward would
+ * launch with these arguments (leaves, grad_out, grad_leaves, slice_ids and
+ * ws fixed in the graph, as for tn_graph_create; the caller may change the
+ * contents of the leaves and of grad_out between launches) and instantiates
+ * it; tn_graph_launch then runs one backward pass, which ADDS the leaf
+ * gradients into grad_leaves like tn_contract_backward (clear them between
+ * launches for a fresh gradient).  Nothing is launched at creation; stream
+ * is unused and may be NULL.  Same errors as tn_contract_backward.  For
+ * training loops of fixed shape, where the adjoint's many small launches
+ * make host overhead the bound.
+ */
+tn_status tn_graph_create_backward(tn_plan_t plan, const void* const* leaves,
+                                   const void* grad_out, void* const* grad_leaves,
+                                   const int64_t* slice_ids, int64_t n_slice_ids, void* ws,
+                                   size_t ws_bytes, void* stream, tn_graph_t* graph);
 
 /*
  * Adjoint of tn_contract with out_mode TN_OUT_SUM over the slices

@@ -102,7 +102,7 @@ EXPORTS = ("tn_plan_create", "tn_plan_query", "tn_plan_step", "tn_contract",
            "tn_contract_probe", "tn_contract_backward", "tn_plan_destroy", "tn_last_error",
            "tn_permute", "tn_plan_chain", "tn_plan_schedule", "tn_plan_segment_tables",
            "tn_contract_noalloc", "tn_plan_backward_tables", "tn_contract_ex",
-           "tn_graph_create", "tn_graph_launch", "tn_graph_destroy")
+           "tn_graph_create", "tn_graph_launch", "tn_graph_destroy", "tn_graph_create_backward")
 TN_CALL_REUSE_INVARIANT = 1
 NOALLOC_WORKSPACE_BYTES = 64 << 20
 
@@ -144,6 +144,10 @@ def lib():
         L.tn_graph_create.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_int64),
                                       ctypes.c_int64, ctypes.c_int32, P, P, ctypes.c_size_t, P,
                                       ctypes.POINTER(P)]
+        L.tn_graph_create_backward.restype = ctypes.c_int
+        L.tn_graph_create_backward.argtypes = [P, ctypes.POINTER(P), P, ctypes.POINTER(P),
+                                               ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, P,
+                                               ctypes.c_size_t, P, ctypes.POINTER(P)]
         L.tn_graph_launch.restype = ctypes.c_int
         L.tn_graph_launch.argtypes = [P, P]
         L.tn_graph_destroy.restype = None
@@ -222,14 +226,18 @@ def load_tune_table(path=TUNE_PATH):
 
 
 class Graph:
-    """An instantiated contraction graph (``tn_graph_create``).  Holds the
-    plan, the leaf tensors, the output and the workspace its kernels use."""
+    """An instantiated contraction graph (``tn_graph_create``) or adjoint
+    graph (``tn_graph_create_backward``).  Holds the plan and every tensor its
+    kernels use: leaves, output (or output gradient and leaf gradients) and
+    workspace."""
 
-    def __init__(self, handle, plan, leaves, out, ws):
+    def __init__(self, handle, plan, leaves, out, ws, keep=()):
         self._h, self.plan, self.leaves, self.out, self._ws = handle, plan, leaves, out, ws
+        self._keep = keep
 
     def launch(self, stream=None):
-        """One contraction of the leaves' current contents into ``out``."""
+        """One contraction of the leaves' current contents into ``out`` (an
+        adjoint graph adds the leaf gradients into its ``out`` list)."""
         _check(lib().tn_graph_launch(self._h, _stream_ptr(stream)))
         return self.out
 
@@ -456,6 +464,23 @@ class Plan:
             ptrs.append(x.data_ptr())
         return self._ptr_array(*ptrs), dev
 
+    def _grad_ptrs(self, grad_leaves, grad_out):
+        """Device pointers of the leaf-gradient buffers (None: skipped), each
+        checked against its leaf's size, and of the output gradient."""
+        import torch
+        if len(grad_leaves) != self.n_tensors:
+            raise ValueError(f"expected {self.n_tensors} gradient buffers, got {len(grad_leaves)}")
+        for t, x in enumerate(grad_leaves):
+            if x is not None and (x.dtype != torch.complex64 or not x.is_contiguous()
+                                  or x.numel() != self._leaf_numel[t]):
+                raise ValueError(f"gradient buffer {t} must be a contiguous complex64 tensor "
+                                 f"of {self._leaf_numel[t]} elements")
+        if grad_out.dtype != torch.complex128 or not grad_out.is_contiguous() or \
+                grad_out.numel() != self._static_info()["out_elems"]:
+            raise ValueError("grad_out must be a contiguous complex128 tensor of the output's size")
+        garr = self._ptr_array(*[(x.data_ptr() if x is not None else None) for x in grad_leaves])
+        return garr, ctypes.c_void_p(grad_out.data_ptr())
+
     def _invariant_key(self, leaves, ws):
         """Key of the invariant leaves' contents: each tensor's identity and
         torch's in-place version counter (the tensors are held, so their
@@ -540,6 +565,29 @@ class Plan:
                                      ctypes.byref(h)))
         return Graph(h, self, list(leaves), out, ws)
 
+    def backward_graph(self, leaves, grad_out, grad_leaves, slice_ids=None):
+        """``tn_graph_create_backward``: the adjoint of these leaves as a HIP
+        graph on the plan's backward workspace.  ``grad_out`` (complex128,
+        the output's shape) and ``grad_leaves`` (complex64 like the leaves, or
+        None) are fixed in the graph: change their contents in place; each
+        ``Graph.launch()`` adds the leaf gradients into ``grad_leaves``."""
+        import torch
+        inf = self._static_info()
+        arr, dev = self._leaf_ptrs(leaves)
+        ws = self._workspace(inf["workspace_backward_bytes"], dev, "_ws_bwd")
+        garr, gp = self._grad_ptrs(grad_leaves, grad_out)
+        if slice_ids is not None:
+            sids = np.ascontiguousarray(np.asarray(slice_ids, dtype=np.int64))
+            sp = sids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+            nsel = len(sids)
+        else:
+            sids, sp, nsel = None, None, 0
+        h = ctypes.c_void_p()
+        _check(lib().tn_graph_create_backward(self._h, arr, gp,
+                                              garr, sp, nsel, ctypes.c_void_p(ws.data_ptr()),
+                                              ws.numel(), None, ctypes.byref(h)))
+        return Graph(h, self, list(leaves), list(grad_leaves), ws, keep=(grad_out,))
+
     def contract_noalloc(self, leaves, out, slice_ids=None, per_slice=False, stream=None):
         """``tn_contract_noalloc``: the library's own static workspace, the
         caller's ``out`` (complex128, shaped as ``contract`` returns it)."""
@@ -563,15 +611,14 @@ class Plan:
         arr, dev = self._leaf_ptrs(leaves)
         ws = self._workspace(inf["workspace_backward_bytes"], dev, "_ws_bwd")
         g = grad_out.to(torch.complex128).contiguous()
-        garr = (ctypes.c_void_p * self.n_tensors)(
-            *[(x.data_ptr() if x is not None else None) for x in grad_leaves])
+        garr, gp = self._grad_ptrs(grad_leaves, g)
         if slice_ids is not None:
             sids = np.ascontiguousarray(np.asarray(slice_ids, dtype=np.int64))
             sp = sids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
             nsel = len(sids)
         else:
             sids, sp, nsel = None, None, 0
-        _check(lib().tn_contract_backward(self._h, arr, ctypes.c_void_p(g.data_ptr()), garr, sp,
+        _check(lib().tn_contract_backward(self._h, arr, gp, garr, sp,
                                           nsel, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                           _stream_ptr(stream)))
         return grad_leaves

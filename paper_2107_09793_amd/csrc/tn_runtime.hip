@@ -1298,15 +1298,10 @@ struct tn_graph_s {
   }
 };
 
-tn_status tn_graph_create(tn_plan_t plan, const void* const* leaves, const int64_t* slice_ids,
-                          int64_t n_slice_ids, int32_t out_mode, void* out, void* ws,
-                          size_t ws_bytes, void* stream, tn_graph_t* graph) {
-  (void)stream;
-  if (!graph) return fail(TN_E_INVALID, "graph is NULL");
-  *graph = nullptr;
-  if (!plan) return fail(TN_E_INVALID, "NULL plan");
-  if (!plan->p.segments.empty())
-    return fail(TN_E_UNSUPPORTED, "plans with persistent segments are not captured");
+// Records the launches `body` makes on an internal non-blocking stream
+// (default priority) into a graph and instantiates it; nothing runs.
+static tn_status capture_graph(const std::function<tn_status(hipStream_t)>& body,
+                               tn_graph_t* graph) {
   hipStream_t cs = nullptr;
   TN_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   tn_graph_s* g = nullptr;
@@ -1322,15 +1317,14 @@ tn_status tn_graph_create(tn_plan_t plan, const void* const* leaves, const int64
     (void)hipStreamDestroy(cs);
     return fail(TN_E_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
   }
-  tn_status s = contract_impl(plan, leaves, slice_ids, n_slice_ids, out_mode, out, ws, ws_bytes,
-                              cs, nullptr);
+  tn_status s = body(cs);
   hipGraph_t captured = nullptr;
   e = hipStreamEndCapture(cs, &captured);   // ends the capture on every path
   (void)hipStreamDestroy(cs);
   g->graph = captured;
   if (s != TN_OK) {
     delete g;
-    return s;   // tn_last_error holds contract_impl's message
+    return s;   // tn_last_error holds the body's message
   }
   if (e != hipSuccess || !captured) {
     delete g;
@@ -1343,6 +1337,23 @@ tn_status tn_graph_create(tn_plan_t plan, const void* const* leaves, const int64
   }
   *graph = g;
   return TN_OK;
+}
+
+tn_status tn_graph_create(tn_plan_t plan, const void* const* leaves, const int64_t* slice_ids,
+                          int64_t n_slice_ids, int32_t out_mode, void* out, void* ws,
+                          size_t ws_bytes, void* stream, tn_graph_t* graph) {
+  (void)stream;
+  if (!graph) return fail(TN_E_INVALID, "graph is NULL");
+  *graph = nullptr;
+  if (!plan) return fail(TN_E_INVALID, "NULL plan");
+  if (!plan->p.segments.empty())
+    return fail(TN_E_UNSUPPORTED, "plans with persistent segments are not captured");
+  return capture_graph(
+      [&](hipStream_t cs) {
+        return contract_impl(plan, leaves, slice_ids, n_slice_ids, out_mode, out, ws, ws_bytes,
+                             cs, nullptr);
+      },
+      graph);
 }
 
 tn_status tn_graph_launch(tn_graph_t graph, void* stream) {
@@ -1403,7 +1414,7 @@ tn_status tn_contract_noalloc(tn_plan_t plan, const void* const* leaves, const i
 
 extern "C" {
 
-tn_status tn_contract_backward(tn_plan_t plan, const void* const* leaves, const void* grad_out,
+static tn_status backward_impl(tn_plan_t plan, const void* const* leaves, const void* grad_out,
                                void* const* grad_leaves, const int64_t* slice_ids,
                                int64_t n_slice_ids, void* ws, size_t ws_bytes, void* stream) {
   if (!plan || !leaves || !grad_out || !grad_leaves) return fail(TN_E_INVALID, "NULL argument");
@@ -1641,6 +1652,29 @@ tn_status tn_contract_backward(tn_plan_t plan, const void* const* leaves, const 
   }
   if ((s = adjoint(0, n0, 0)) != TN_OK) return s;
   return tb.flush();
+}
+
+tn_status tn_contract_backward(tn_plan_t plan, const void* const* leaves, const void* grad_out,
+                               void* const* grad_leaves, const int64_t* slice_ids,
+                               int64_t n_slice_ids, void* ws, size_t ws_bytes, void* stream) {
+  return backward_impl(plan, leaves, grad_out, grad_leaves, slice_ids, n_slice_ids, ws, ws_bytes,
+                       stream);
+}
+
+tn_status tn_graph_create_backward(tn_plan_t plan, const void* const* leaves,
+                                   const void* grad_out, void* const* grad_leaves,
+                                   const int64_t* slice_ids, int64_t n_slice_ids, void* ws,
+                                   size_t ws_bytes, void* stream, tn_graph_t* graph) {
+  (void)stream;
+  if (!graph) return fail(TN_E_INVALID, "graph is NULL");
+  *graph = nullptr;
+  if (!plan) return fail(TN_E_INVALID, "NULL plan");
+  return capture_graph(
+      [&](hipStream_t cs) {
+        return backward_impl(plan, leaves, grad_out, grad_leaves, slice_ids, n_slice_ids, ws,
+                             ws_bytes, cs);
+      },
+      graph);
 }
 
 tn_status tn_permute(const void* in, void* out, int32_t nbits, const int8_t* in_log2,
