@@ -38,12 +38,15 @@ __global__ void __launch_bounds__(kBlock) k_simple(StepArgs p) {
 // come by level (a step's operands are produced by steps of lower levels or
 // before the batch, and no step writes what another step of its level reads
 // or writes); the outputs of all steps of one level are spread over
-// the workgroup's threads, each formed as k_simple forms it, and a
+// the workgroup's 1024 threads, each formed as k_simple forms it, and a
 // workgroup barrier separates the levels (a level's results are visible to
 // every wave of the workgroup once it is passed).  No workgroup waits on
 // another, and the descriptors travel in the kernel arguments.
 constexpr int kTinyMax = 20;
 constexpr int kTinyClassBits = 14;
+// threads of the batch's workgroup: a step's outputs (at most 2^10) take one
+// pass, and a level's several steps spread over 16 waves
+constexpr int kTinyBlock = 1024;
 struct TinyStep {
   const float2* A;
   const float2* B;
@@ -63,7 +66,7 @@ static_assert(sizeof(TinyArgs) <= 4000, "kernel arguments");
 
 static_assert(sizeof(TinyArgs) % 4 == 0, "descriptor copy in 32-bit words");
 
-__global__ void __launch_bounds__(kBlock) k_tiny_run(TinyArgs args) {
+__global__ void __launch_bounds__(kTinyBlock) k_tiny_run(TinyArgs args) {
   // the descriptors go to LDS once: every output of every level looks up its
   // step's sizes and strides, and from the kernel arguments (indexed per
   // thread) each lookup would be a dependent memory round trip
@@ -71,7 +74,7 @@ __global__ void __launch_bounds__(kBlock) k_tiny_run(TinyArgs args) {
   {
     const uint32_t* src = reinterpret_cast<const uint32_t*>(&args);
     uint32_t* dst = reinterpret_cast<uint32_t*>(&a);
-    for (int i = threadIdx.x; i < (int)(sizeof(TinyArgs) / 4); i += kBlock) dst[i] = src[i];
+    for (int i = threadIdx.x; i < (int)(sizeof(TinyArgs) / 4); i += kTinyBlock) dst[i] = src[i];
   }
   __syncthreads();
   int s = 0;
@@ -81,7 +84,7 @@ __global__ void __launch_bounds__(kBlock) k_tiny_run(TinyArgs args) {
     while (e < a.n && a.st[e].level == lv) ++e;
     uint32_t total = 0;
     for (int j = s; j < e; ++j) total += 1u << (a.st[j].nb + a.st[j].nm + a.st[j].nn);
-    for (uint32_t f = threadIdx.x; f < total; f += kBlock) {
+    for (uint32_t f = threadIdx.x; f < total; f += kTinyBlock) {
       int j = s;
       uint32_t o = f;
       while (o >= (1u << (a.st[j].nb + a.st[j].nm + a.st[j].nn))) {

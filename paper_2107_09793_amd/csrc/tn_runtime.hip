@@ -447,7 +447,7 @@ tn_status launch_tiny(const Ctx& c, const tn::Segment& g, uint64_t outer_val, Pr
     timed |= probe && !probe->done && probe->step == k;
   }
   if (timed) TN_HIP_CHECK(hipEventRecord(probe->start, c.st));
-  hipLaunchKernelGGL(tnk::k_tiny_run, dim3(1), dim3(tnk::kBlock), 0, c.st, a);
+  hipLaunchKernelGGL(tnk::k_tiny_run, dim3(1), dim3(tnk::kTinyBlock), 0, c.st, a);
   TN_HIP_CHECK(hipGetLastError());
   if (timed) {
     TN_HIP_CHECK(hipEventRecord(probe->stop, c.st));
@@ -529,7 +529,7 @@ class TinyBatcher {
     }
     n_ = 0;
     ++launches_;
-    hipLaunchKernelGGL(tnk::k_tiny_run, dim3(1), dim3(tnk::kBlock), 0, st_, t);
+    hipLaunchKernelGGL(tnk::k_tiny_run, dim3(1), dim3(tnk::kTinyBlock), 0, st_, t);
     TN_HIP_CHECK(hipGetLastError());
     return TN_OK;
   }
