@@ -83,8 +83,8 @@ typedef enum { TN_OUT_SUM = 0, TN_OUT_PER_SLICE = 1 } tn_out_mode;
 #define TN_FLAG_FIT_BACKWARD 256u  /* the resident / outer split also keeps
                                      info.workspace_backward_bytes within
                                      workspace_limit (plans used for gradients)      */
-#define TN_FLAG_NO_TINY 512u      /* run tiny steps (at most 2^12 multiply-adds and
-                                     2^10 outputs) one launch each instead of in
+#define TN_FLAG_NO_TINY 512u      /* run tiny steps (at most 2^13 multiply-adds and
+                                     2^11 outputs) one launch each instead of in
                                      batches of up to 20 consecutive ones per launch
                                      of one workgroup (forward batches are formed
                                      only without TN_FLAG_PERSISTENT); the same for

@@ -33,8 +33,8 @@ __global__ void __launch_bounds__(kBlock) k_simple(StepArgs p) {
 }
 
 // ---------------------------------------------------------------------------
-// A batch of tiny steps (consecutive in the schedule, each at most 2^12
-// multiply-adds and 2^10 outputs) in one launch of one workgroup.  The steps
+// A batch of tiny steps (consecutive in the schedule, each at most 2^13
+// multiply-adds and 2^11 outputs) in one launch of one workgroup.  The steps
 // come by level (a step's operands are produced by steps of lower levels or
 // before the batch, and no step writes what another step of its level reads
 // or writes); the outputs of all steps of one level are spread over
@@ -44,8 +44,8 @@ __global__ void __launch_bounds__(kBlock) k_simple(StepArgs p) {
 // another, and the descriptors travel in the kernel arguments.
 constexpr int kTinyMax = 20;
 constexpr int kTinyClassBits = 14;
-// threads of the batch's workgroup: a step's outputs (at most 2^10) take one
-// pass, and a level's several steps spread over 16 waves
+// threads of the batch's workgroup: a step's outputs (at most 2^11) take one
+// or two passes, and a level's several steps spread over 16 waves
 constexpr int kTinyBlock = 1024;
 struct TinyStep {
   const float2* A;

@@ -55,8 +55,8 @@ constexpr int kTinyClassBits = 14;      // per class, to fit the kernel argument
 // a tiny step: at most 2^kTinyCmacBits complex multiply-adds and
 // 2^kTinyOutBits outputs, so that the one workgroup running a batch gives
 // each thread a few outputs (the loads of one output wait on each other)
-constexpr int kTinyCmacBits = 12;
-constexpr int kTinyOutBits = 10;
+constexpr int kTinyCmacBits = 13;
+constexpr int kTinyOutBits = 11;
 constexpr int64_t kSmallStepBytes = 272; // sizeof the device descriptor
 constexpr int64_t kCtrStride = 32;       // int32 slots between completion counters
 
